@@ -1,0 +1,209 @@
+"""Benchmark: time-to-solve of a 512^3 two-phase RVE to relative residual 1e-6,
+mixed form vs float64 form, on one MI355X.
+
+A step is one whole solve with the conductivity already resident in HBM:
+etc_setup (canonical copy, extrema, reference medium, tables) + etc_solve
+(PCG to rtol) + etc_keff.  Prints one JSON line (rank 0, N = 1).
+
+Workload ("spheres512"): 512^3 voxels, non-overlapping spheres of radius 10
+voxels added by random sequential addition (seed 4) until the voxel volume
+fraction reaches 0.26 (8660 spheres), kappa 1 in the matrix and 100 in the
+spheres, load along x, Dirichlet 1 / 0.
+
+Extra fields: the float64 form's time, both K_eff values and iteration
+counts, the achieved HBM rate of the whole solve (algorithmic bytes / time),
+the roofline record of the dominant kernel (HIP-event timing around its
+launches inside the timed region) and the CPU oracle's time on a bounded
+sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solve 512^3 RVE at rel.res 1e-6 (mixed vs FP64); achieved HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per voxel and launch of each hot kernel (reads +
+# writes of the arrays it must touch), by storage precision.
+#   1 operator:           w, kappa -> q                         3 vectors
+#   2 update + DCT_b:     p(8), w, r, q -> p(8), r, t           p double + 5 vectors
+#   3 DCT_a forward:      t -> t                                2 vectors
+#   4 tridiagonal:        t -> t                                2 vectors
+#   5 DCT_a backward:     t -> t                                2 vectors
+#   6 DCT_b^-1 + direction: t, w -> w                           3 vectors
+KERNEL_NAMES = {1: "k_apply_A", 2: "k_rows_fwd (update + DCT_b)", 3: "k_cols (DCT_a forward)",
+                4: "k_thomas", 5: "k_cols (DCT_a backward)", 6: "k_rows_inv (DCT_b^-1 + direction)"}
+
+
+def bytes_per_voxel(kernel: int, es: int) -> int:
+    return {1: 3 * es, 2: 16 + 5 * es, 3: 2 * es, 4: 2 * es, 5: 2 * es, 6: 3 * es}[kernel]
+
+
+def iteration_bytes_per_voxel(es: int, mixed: bool, refine_every: int) -> float:
+    b = sum(bytes_per_voxel(k, es) for k in range(1, 7))
+    if mixed and refine_every > 0:
+        # true residual (p double, kappa, r) + redo of DCT_b (r -> t), every refine_every passes
+        b += (8 + es + es + 2 * es) / refine_every
+    return b
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2404_02433_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: int, workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(str(kernel))
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def run_solve(etc, kap, precision, rtol, timer_kernel=0):
+    plan = etc.etc_setup(kap, 0, 1.0, 0.0, precision=precision, rtol=rtol)
+    if timer_kernel:
+        etc.etc_set_kernel_timer(plan, timer_kernel)
+    out = etc.etc_solve(plan)
+    out.update(etc.etc_keff(plan))
+    if timer_kernel:
+        out["kernel_ms"], out["kernel_launches"] = etc.etc_kernel_time(plan)
+    plan.close()
+    return out
+
+
+def time_form(torch, etc, kap, precision, rtol, steps, warmup, timer_kernel):
+    for _ in range(warmup):
+        run_solve(etc, kap, precision, rtol)
+    torch.cuda.synchronize()
+    outs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs.append(run_solve(etc, kap, precision, rtol, timer_kernel))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, outs
+
+
+def cpu_baseline(kap_np, iters_full: int, sample_iters: int = 2):
+    """Oracle (float64 NumPy) on the host: setup plus `sample_iters` PCG
+    passes of the same 512^3 workload, scaled to the GPU's pass count."""
+    import numpy as np  # noqa: F401
+
+    from oracle import etc_oracle as O
+
+    t0 = time.perf_counter()
+    pb = O.make_problem(kap_np, 0)
+    kref = O.kref_mid(pb)
+    t_setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    res = O.pcg(pb, rtol=1e-6, max_iter=sample_iters, kref=kref)
+    t_pcg = time.perf_counter() - t1
+    per_iter = t_pcg / max(1, res.iters + 1)   # initial preconditioner pass + sample passes
+    est = t_setup + per_iter * (iters_full + 1)
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"512^3 spheres512: oracle setup + initial pass + {res.iters} PCG passes timed "
+                      f"({t_setup + t_pcg:.1f} s), scaled to {iters_full} passes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="grid edge (default: the 512^3 workload)")
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--kernel", type=int, default=2, help="hot kernel timed with HIP events (1-6)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--forms", default="mixed,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2404_02433_amd as etc
+    import rvegen
+
+    print(f"bench: generating spheres512 at n={args.n}", file=sys.stderr, flush=True)
+    kap_np, info = rvegen.make_config("spheres512", args.n)
+    kap = torch.as_tensor(kap_np, device="cuda:0")
+    V = kap_np.size
+    forms = args.forms.split(",")
+    res = {}
+    for form in forms:
+        print(f"bench: timing {form}", file=sys.stderr, flush=True)
+        dt, outs = time_form(torch, etc, kap, form, args.rtol, args.steps, args.warmup, args.kernel)
+        o = outs[-1]
+        es = 4 if form == "mixed" else 8
+        it_bytes = iteration_bytes_per_voxel(es, form == "mixed", 10) * V
+        kms = sum(x["kernel_ms"] for x in outs) / max(1, sum(x["kernel_launches"] for x in outs))
+        res[form] = {"time_s": dt, "iters": o["iters"], "keff": o["keff"], "k_in": o["k_in"],
+                     "relres": o["relres"], "status": o["status"],
+                     "hbm_gbs": it_bytes * o["iters"] / dt / 1e9,
+                     "kernel_avg_ms": kms}
+        print(f"bench: {form} {dt:.4f} s/solve iters={o['iters']} keff={o['keff']:.8f}", file=sys.stderr, flush=True)
+
+    head = "mixed" if "mixed" in res else forms[0]
+    es = 4 if head == "mixed" else 8
+    kid = args.kernel
+    bpl = bytes_per_voxel(kid, es) * V
+    kms = res[head]["kernel_avg_ms"]
+    achieved = bpl / (kms * 1e-3) / 1e9 if kms > 0 else None
+    traffic = measured_traffic(kid, "spheres512", head)
+    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[kid], "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "algorithmic_bytes_per_launch": bpl, "avg_launch_ms": kms}
+    line = {
+        "metric": METRIC,
+        "value": res[head]["time_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res[head]["time_s"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage / f64 dots+tridiagonal+refinement" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"spheres512: {args.n}^3 two-phase RVE, r=10 non-overlapping spheres to "
+                               f"vf>={0.26} ({info['spheres']} spheres, vf={info['vf']:.4f}), kappa 1/100, "
+                               f"load x, rtol {args.rtol:g}", "form": head},
+        "forms": res,
+        "keff_mixed_vs_fp64": (abs(res["mixed"]["keff"] - res["fp64"]["keff"]) / res["fp64"]["keff"]
+                               if "mixed" in res and "fp64" in res else None),
+        "hbm_gbs": res[head]["hbm_gbs"],
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        print("bench: cpu oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(kap_np, res[head]["iters"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * etc.h — C ABI of the MI355X (gfx950) effective-thermal-conductivity solver.
+ *
+ * Method (Ye, Fu and Chung, arXiv 2404.02433):
+ *   - steady conduction -div(K grad p) = 0 on a voxel RVE with constant
+ *     Dirichlet data p_in / p_out on the two faces normal to the load axis and
+ *     zero flux on the other four (Section "Model problem");
+ *   - Two-Point Flux-Approximation: one unknown per voxel, internal-face
+ *     conductivity = harmonic mean of the two cells, Dirichlet faces 2 kappa
+ *     (Section "Discretization scheme", eq:flux, eq:scaled bilinear forms);
+ *   - preconditioned conjugate gradients (alg:pcg) with the exit test
+ *     ||r||_2 / ||b||_2 <= rtol (eq:exit);
+ *   - preconditioner = homogeneous reference medium (eq:refer bilinear forms)
+ *     solved by DCTs along the two transverse axes and one tridiagonal solve
+ *     per transverse mode along the load axis (alg:solve ref);
+ *   - reference parameters from the family extrema of
+ *     eq:parameters for linear programming (alg:refer parameters);
+ *   - effective conductivity from the outflow-face flux
+ *     (eq:effective formula dis).
+ *
+ * Conventions shared by every entry point:
+ *   - Conductivity and solution arrays given by the caller are C-contiguous
+ *     device arrays of shape n[0] x n[1] x n[2] (user layout).  `axis` names
+ *     the load axis; the two other axes are the transverse ones.
+ *   - Internally the plan keeps a canonical layout [k][a][b]: load axis k
+ *     slowest, the two transverse axes after it in their user order, b
+ *     contiguous.  Entry points marked "canonical" take vectors in that layout.
+ *   - Voxel edges h_d = L[d] / n[d] (cubic voxels of edge 1 when L is all
+ *     zeros); the scaled conductivity of a face normal to d is kappa / h_d^2.
+ *   - Every call is enqueued on the plan's HIP stream.  Calls returning host
+ *     values synchronise that stream.
+ *   - A plan is not thread-safe; separate plans may run concurrently on
+ *     separate streams.
+ *   - Errors: every call returns an etc_status; nothing throws across the ABI.
+ *     etc_last_error() gives a message for the last failure on this thread.
+ */
+#ifndef ETC_H
+#define ETC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ETC_OK = 0,
+  ETC_NOT_CONVERGED = 1,   /* warning: iteration cap reached; results stay readable */
+  ETC_E_INVALID = -1,      /* bad argument or bad conductivity (<= 0, NaN, Inf)      */
+  ETC_E_NOMEM = -2,        /* device allocation failed or caller workspace too small */
+  ETC_E_HIP = -3,          /* a HIP runtime call failed                              */
+  ETC_E_BREAKDOWN = -4,    /* w.Aw <= 0, r.z <= 0 or a non-finite scalar in PCG      */
+  ETC_E_STATE = -5,        /* result requested before a successful etc_solve         */
+  ETC_E_UNSUPPORTED = -6   /* a size beyond the kernels' limits                       */
+} etc_status;
+
+typedef enum { ETC_F64 = 0, ETC_F32 = 1 } etc_dtype;
+
+/* ETC_FP64: every vector float64.  ETC_MIXED: iteration vectors and the
+ * stencil/DCT arithmetic in float32, tridiagonal solves, dot products and
+ * PCG scalars in float64, solution p in float64, and the residual replaced by
+ * the float64 true residual b - A p every `refine_every` passes and before
+ * convergence is accepted. */
+typedef enum { ETC_FP64 = 0, ETC_MIXED = 1 } etc_precision;
+
+/* Reference parameters: MID = sqrt(min * max) of each family (an optimum of
+ * eq:linear programming); ONE = all 1 (the paper's "one"); USER = kref_user. */
+typedef enum { ETC_KREF_MID = 0, ETC_KREF_ONE = 1, ETC_KREF_USER = 2 } etc_kref_mode;
+
+/* Dirichlet pair on the faces normal to the load axis (p_in at index 0). */
+typedef struct {
+  double p_in, p_out;
+} etc_bc;
+
+typedef struct {
+  etc_precision precision;
+  etc_kref_mode kref_mode;
+  double kref_user[5];   /* order: load-axis faces, a faces, b faces, in layer, out layer */
+  double rtol;           /* default 1e-6 */
+  int max_iter;          /* default 1000 */
+  int refine_every;      /* mixed form: true-residual period, default 10 */
+  int poll_every;        /* passes enqueued between host checks, default 8 */
+  void* stream;          /* hipStream_t; NULL = the null stream */
+  double L[3];           /* domain length per user axis; all 0 = voxel edge 1 */
+  void* workspace;       /* optional caller-owned device memory (>= etc_workspace_size) */
+  size_t workspace_bytes;
+} etc_options;
+
+typedef struct {
+  int iters;             /* PCG passes (products A w) */
+  int status;            /* etc_status of the solve */
+  double relres;         /* last relative residual (true residual in the mixed form) */
+  double kref[5];        /* reference parameters used (order as kref_user) */
+  double lambda_lo, lambda_hi; /* Lambda', Lambda'' of lem:cond for these parameters */
+} etc_result;
+
+typedef struct etc_plan etc_plan;
+
+/* Fill `opt` with the defaults listed above. */
+void etc_options_default(etc_options* opt);
+
+/* Device bytes a plan for this size, input dtype and options needs.  Same
+ * argument rules as etc_setup.  Returns ETC_E_INVALID on bad sizes. */
+etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const etc_options* opt, size_t* bytes);
+
+/* Preparation phase (the paper separates preparation from execution, Section
+ * "Performance tests of different implementations"): validates the arguments,
+ * copies `kappa` (device, user layout, dtype `dt`) into the canonical layout,
+ * checks every conductivity is finite and > 0, computes the family extrema and
+ * the reference parameters, and builds the DCT twiddle and eigenvalue tables.
+ *   kappa : borrowed for the duration of the call only.
+ *   n     : user dims; each >= 1, n[axis] >= 2, product < 2^31 per plane.
+ *   bc    : p_in != p_out (eq:effective formula needs a drop).
+ *   opt   : may be NULL (defaults).  If opt->workspace is NULL the plan
+ *           allocates its device memory with hipMalloc and frees it in
+ *           etc_destroy; otherwise it carves the caller's buffer (caller keeps
+ *           ownership and must keep it alive until etc_destroy).
+ *   plan  : receives the new plan (NULL on failure). */
+etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                     const etc_options* opt, etc_plan** plan);
+
+/* Execution phase: PCG of alg:pcg from p0 (device, user layout, float64;
+ * NULL = zero) until ||r|| / ||b|| <= rtol or max_iter passes.  Returns
+ * ETC_OK, ETC_NOT_CONVERGED (results still readable) or an error.  `res` may
+ * be NULL.  Synchronises the plan's stream. */
+etc_status etc_solve(etc_plan* plan, const double* p0, etc_result* res);
+
+/* Effective conductivity along the load axis after etc_solve (host doubles):
+ *   k_out    : eq:effective formula dis (outflow-face flux);
+ *   k_in     : same with the inflow faces (nullable);
+ *   k_energy : from the discrete dissipation (nullable; one extra pass).
+ * ETC_E_STATE before a solve. */
+etc_status etc_keff(etc_plan* plan, double* k_out, double* k_in, double* k_energy);
+
+/* Copy the solution p into `p` (device, user layout, float64, caller-owned). */
+etc_status etc_get_solution(const etc_plan* plan, double* p);
+
+/* Relative-residual history of the last solve: hist[0] = 1 (p0 = 0) up to
+ * hist[iters]; copies min(cap, iters + 1) values to host memory. */
+etc_status etc_residual_history(const etc_plan* plan, double* hist, int cap, int* count);
+
+/* Canonical-layout building blocks of one PCG pass, for callers that drive
+ * their own iteration.  Vectors are device arrays of V = n[0] n[1] n[2]
+ * elements in the plan's storage dtype (float64 for ETC_FP64, float32 for
+ * ETC_MIXED).
+ *   etc_apply_A    : y = A x (eq:scaled bilinear forms); *xAx = x . y if non-NULL.
+ *   etc_apply_Minv : z = A_ref^{-1} r by alg:solve ref; *rz = r . z if non-NULL.
+ * Both synchronise when a dot is requested.  x/y and r/z must not alias. */
+etc_status etc_apply_A(etc_plan* plan, const void* x, void* y, double* xAx);
+etc_status etc_apply_Minv(etc_plan* plan, const void* r, void* z, double* rz);
+
+/* Per-kernel timing with HIP events recorded around every launch of one hot
+ * kernel on the plan's stream during etc_solve.  kernel_id: 0 off,
+ * 1 operator, 2 update + forward row DCT, 3 forward column DCT,
+ * 4 tridiagonal solve, 5 backward column DCT, 6 backward row DCT + direction.
+ * etc_kernel_time returns the summed milliseconds and launch count of the
+ * last solve. */
+etc_status etc_set_kernel_timer(etc_plan* plan, int kernel_id);
+etc_status etc_kernel_time(const etc_plan* plan, double* total_ms, int* launches);
+
+/* Device-to-device copy of n doubles by a plain streaming kernel (used to
+ * calibrate hardware byte counters). */
+etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream);
+
+void etc_destroy(etc_plan* plan);
+
+/* Message of the last failed call on the calling thread ("" if none). */
+const char* etc_last_error(void);
+
+/* Library version string. */
+const char* etc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETC_H */

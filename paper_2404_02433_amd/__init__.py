@@ -1,0 +1,329 @@
+"""MI355X (gfx950) effective-thermal-conductivity solver: Python binding.
+
+Thin ctypes layer over ``libetc.so`` (C ABI declared in ``include/etc.h``).
+It only marshals arguments: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (the plan's workspace is a torch
+tensor) and the current HIP stream.  There is no CPU fallback: if the library
+is missing, importing the binding's functions raises.
+
+Entry points keep the C names: ``etc_setup``, ``etc_solve``, ``etc_keff``,
+``etc_get_solution``, ``etc_residual_history``, ``etc_apply_A``,
+``etc_apply_Minv``, ``etc_destroy``, ``etc_last_error``; ``solve`` chains
+setup, solve and K_eff for one call.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "EtcError", "library_path", "load_library", "etc_workspace_size", "etc_setup", "etc_solve", "etc_keff",
+    "etc_get_solution", "etc_residual_history", "etc_apply_A", "etc_apply_Minv", "etc_set_kernel_timer",
+    "etc_kernel_time", "etc_copy_f64", "etc_destroy", "etc_last_error", "etc_version", "Plan", "solve",
+    "STATUS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+STATUS = {0: "ok", 1: "not_converged", -1: "invalid", -2: "nomem", -3: "hip", -4: "breakdown", -5: "state",
+          -6: "unsupported"}
+_PREC = {"fp64": 0, "mixed": 1}
+_KREF = {"mid": 0, "one": 1, "user": 2}
+_DTYPE = {"float64": 0, "float32": 1}
+
+
+class EtcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"etc status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class _BC(ctypes.Structure):
+    _fields_ = [("p_in", ctypes.c_double), ("p_out", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("kref_mode", ctypes.c_int),
+        ("kref_user", ctypes.c_double * 5),
+        ("rtol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("refine_every", ctypes.c_int),
+        ("poll_every", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("L", ctypes.c_double * 3),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("relres", ctypes.c_double),
+        ("kref", ctypes.c_double * 5),
+        ("lambda_lo", ctypes.c_double),
+        ("lambda_hi", ctypes.c_double),
+    ]
+
+
+_SYMBOLS = {
+    "etc_options_default": (None, [ctypes.POINTER(_Options)]),
+    "etc_workspace_size": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]),
+    "etc_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC, ctypes.c_int,
+                                 ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]),
+    "etc_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]),
+    "etc_keff": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]),
+    "etc_get_solution": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "etc_residual_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int)]),
+    "etc_apply_A": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "etc_apply_Minv": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "etc_set_kernel_timer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "etc_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+    "etc_copy_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "etc_destroy": (None, [ctypes.c_void_p]),
+    "etc_last_error": (ctypes.c_char_p, []),
+    "etc_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libetc.so")
+
+
+def load_library():
+    """Load libetc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2404_02433_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SYMBOLS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def etc_last_error() -> str:
+    return load_library().etc_last_error().decode()
+
+
+def etc_version() -> str:
+    return load_library().etc_version().decode()
+
+
+def _check(status: int, allow_not_converged: bool = False) -> int:
+    if status == 0 or (allow_not_converged and status == 1):
+        return status
+    raise EtcError(status, etc_last_error())
+
+
+def _torch():
+    import torch  # device memory and streams only
+
+    return torch
+
+
+def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_every=8, kref="mid",
+             kref_user=None, L=None, stream=None) -> _Options:
+    lib = load_library()
+    o = _Options()
+    lib.etc_options_default(ctypes.byref(o))
+    o.precision = _PREC[precision]
+    o.kref_mode = _KREF[kref]
+    if kref_user is not None:
+        for i in range(5):
+            o.kref_user[i] = float(kref_user[i])
+    o.rtol = float(rtol)
+    o.max_iter = int(max_iter)
+    o.refine_every = int(refine_every)
+    o.poll_every = int(poll_every)
+    if L is not None:
+        for d in range(3):
+            o.L[d] = float(L[d])
+    o.stream = stream
+    return o
+
+
+def _dims(shape):
+    if len(shape) != 3:
+        raise ValueError("kappa must be a 3D array")
+    return (ctypes.c_int64 * 3)(*[int(s) for s in shape])
+
+
+def etc_workspace_size(shape, dtype="float64", axis=0, **opts) -> int:
+    o = _options(**opts)
+    out = ctypes.c_size_t(0)
+    _check(load_library().etc_workspace_size(_dims(shape), _DTYPE[dtype], int(axis), ctypes.byref(o),
+                                             ctypes.byref(out)))
+    return int(out.value)
+
+
+class Plan:
+    """Owns a C plan handle, its torch workspace and the stream it runs on."""
+
+    def __init__(self, handle, workspace, kappa_shape, axis, precision, device, stream):
+        self.handle = handle
+        self.workspace = workspace
+        self.shape = tuple(kappa_shape)
+        self.axis = axis
+        self.precision = precision
+        self.device = device
+        self.stream = stream
+        order = [axis] + [d for d in range(3) if d != axis]
+        self.canonical_shape = tuple(self.shape[d] for d in order)
+
+    @property
+    def storage_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.precision == "mixed" else torch.float64
+
+    def close(self):
+        if self.handle:
+            load_library().etc_destroy(self.handle)
+            self.handle = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
+              rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
+              kref: str = "mid", kref_user=None, L=None) -> Plan:
+    """Preparation phase on a device tensor ``kappa`` (float64 or float32,
+    user layout, load axis ``axis``)."""
+    torch = _torch()
+    if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda":
+        raise ValueError("kappa must be a torch tensor on a GPU device")
+    if kappa.dtype not in (torch.float64, torch.float32):
+        raise ValueError("kappa must be float64 or float32")
+    kappa = kappa.contiguous()
+    dtype = "float64" if kappa.dtype == torch.float64 else "float32"
+    stream = torch.cuda.current_stream(kappa.device)
+    o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream)
+    n = _dims(kappa.shape)
+    nbytes = ctypes.c_size_t(0)
+    _check(load_library().etc_workspace_size(n, _DTYPE[dtype], int(axis), ctypes.byref(o), ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=kappa.device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = int(nbytes.value)
+    h = ctypes.c_void_p(0)
+    _check(load_library().etc_setup(kappa.data_ptr(), _DTYPE[dtype], n, _BC(float(p_in), float(p_out)), int(axis),
+                                    ctypes.byref(o), ctypes.byref(h)))
+    return Plan(h, ws, kappa.shape, int(axis), precision, kappa.device, stream)
+
+
+def etc_solve(plan: Plan, p0=None) -> dict:
+    r = _Result()
+    ptr = None
+    if p0 is not None:
+        torch = _torch()
+        if p0.dtype != torch.float64 or tuple(p0.shape) != plan.shape:
+            raise ValueError("p0 must be float64 with kappa's shape")
+        p0 = p0.contiguous()
+        ptr = p0.data_ptr()
+    st = _check(load_library().etc_solve(plan.handle, ptr, ctypes.byref(r)), allow_not_converged=True)
+    return {"iters": r.iters, "status": STATUS[st], "relres": r.relres, "kref": list(r.kref),
+            "lambda_lo": r.lambda_lo, "lambda_hi": r.lambda_hi}
+
+
+def etc_keff(plan: Plan, energy: bool = False) -> dict:
+    ko, ki, ke = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().etc_keff(plan.handle, ctypes.byref(ko), ctypes.byref(ki),
+                                   ctypes.byref(ke) if energy else None))
+    out = {"keff": ko.value, "k_in": ki.value}
+    if energy:
+        out["k_energy"] = ke.value
+    return out
+
+
+def etc_get_solution(plan: Plan):
+    torch = _torch()
+    p = torch.empty(plan.shape, dtype=torch.float64, device=plan.device)
+    _check(load_library().etc_get_solution(plan.handle, p.data_ptr()))
+    return p
+
+
+def etc_residual_history(plan: Plan, cap: int = 100000):
+    buf = (ctypes.c_double * cap)()
+    n = ctypes.c_int(0)
+    _check(load_library().etc_residual_history(plan.handle, buf, cap, ctypes.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def _canon_vec(plan: Plan, x):
+    torch = _torch()
+    if x.dtype != plan.storage_dtype or tuple(x.shape) != plan.canonical_shape:
+        raise ValueError(f"expected a {plan.storage_dtype} tensor of canonical shape {plan.canonical_shape}")
+    return x.contiguous()
+
+
+def etc_apply_A(plan: Plan, x, want_dot: bool = False):
+    """y = A x on canonical-layout vectors of the plan's storage dtype."""
+    torch = _torch()
+    x = _canon_vec(plan, x)
+    y = torch.empty_like(x)
+    d = ctypes.c_double(0.0)
+    _check(load_library().etc_apply_A(plan.handle, x.data_ptr(), y.data_ptr(), ctypes.byref(d) if want_dot else None))
+    return (y, d.value) if want_dot else y
+
+
+def etc_apply_Minv(plan: Plan, r, want_dot: bool = False):
+    """z = A_ref^{-1} r on canonical-layout vectors of the plan's storage dtype."""
+    torch = _torch()
+    r = _canon_vec(plan, r)
+    z = torch.empty_like(r)
+    d = ctypes.c_double(0.0)
+    _check(load_library().etc_apply_Minv(plan.handle, r.data_ptr(), z.data_ptr(),
+                                         ctypes.byref(d) if want_dot else None))
+    return (z, d.value) if want_dot else z
+
+
+def etc_set_kernel_timer(plan: Plan, kernel_id: int):
+    _check(load_library().etc_set_kernel_timer(plan.handle, int(kernel_id)))
+
+
+def etc_kernel_time(plan: Plan):
+    ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+    _check(load_library().etc_kernel_time(plan.handle, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def etc_copy_f64(src, dst):
+    torch = _torch()
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    _check(load_library().etc_copy_f64(src.data_ptr(), dst.data_ptr(), src.numel(), stream))
+
+
+def etc_destroy(plan: Plan):
+    plan.close()
+
+
+def solve(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
+          rtol: float = 1e-6, max_iter: int = 1000, energy: bool = False, return_plan: bool = False, **kw) -> dict:
+    """Setup + solve + K_eff in one call; returns a dict of results."""
+    plan = etc_setup(kappa, axis, p_in, p_out, precision, rtol, max_iter, **kw)
+    out = etc_solve(plan)
+    out.update(etc_keff(plan, energy=energy))
+    if return_plan:
+        out["plan"] = plan
+    else:
+        plan.close()
+    return out

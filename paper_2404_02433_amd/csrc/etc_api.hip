@@ -1,0 +1,895 @@
+// Host side of the ETC library: plan, preparation, PCG driver, results.
+// All solver arithmetic runs in the kernels of etc_kernels.hpp; the host only
+// validates, sizes, launches and polls the device state every few passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "etc.h"
+#include "etc_kernels.hpp"
+
+using namespace etc;
+
+namespace {
+
+thread_local std::string g_err;
+
+etc_status fail(etc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(ETC_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK(name)                                                                         \
+  do {                                                                                          \
+    hipError_t e_ = hipGetLastError();                                                          \
+    if (e_ != hipSuccess) return fail(ETC_E_HIP, std::string("launch ") + name + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kThreads = 256;
+constexpr int kMaxGridStride = 2048;   // grid of the grid-stride reduction kernels
+constexpr int kThomasP = 32;           // partitions per line in the tridiagonal kernel
+constexpr int kThomasTB = 16;          // modes (lines) per tridiagonal block
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct LaunchCfg {
+  // operator / residual: block (64, 4), k chunk
+  dim3 gridA;
+  int kchunk;
+  // rows
+  int rpb, nrows, gridRows;
+  size_t ldsRows;
+  // columns
+  int tb;
+  dim3 gridCols;
+  size_t ldsCols;
+  // tridiagonal
+  dim3 gridThomas;
+  int Puse, maxm;
+  // grid-stride kernels
+  int gridStride;
+  int gridKeff;
+};
+
+}  // namespace
+
+struct etc_plan {
+  Geo g;
+  int64_t n_user[3];
+  int axis;
+  etc_precision prec;
+  etc_dtype in_dt;
+  etc_options opt;
+  hipStream_t stream;
+  // memory
+  bool own_ws;
+  char* ws;
+  size_t ws_bytes;
+  void* kap_s;
+  double* kap_hi;
+  double* p;
+  void *r, *w, *q, *t;
+  double *lam_a, *lam_b;
+  void *tw_a, *tw_b;
+  double* partials;
+  int max_partials;
+  DevState* st;
+  double* hist;
+  DevState* st_host;  // pinned
+  DctPlan dpa, dpb;
+  LaunchCfg lc;
+  double kref[5];
+  double ext[10];
+  double lam_lo, lam_hi;
+  bool solved;
+  int last_iters;
+  int last_status;
+  // kernel timer
+  int timer_id;
+  std::vector<hipEvent_t> ev;
+  int ev_used;
+  double timer_ms;
+  int timer_launches;
+};
+
+namespace {
+
+size_t elt_size(etc_precision prec) { return prec == ETC_MIXED ? sizeof(float) : sizeof(double); }
+
+// Factor M into the radices of the LDS FFT; false if a prime factor > 5 remains.
+bool factor_radices(int M, DctPlan& dp) {
+  dp.nst = 0;
+  int m = M;
+  const int pref[] = {16, 8, 4, 2, 3, 5};
+  for (int r : pref) {
+    while (m % r == 0 && m >= r) {
+      if (dp.nst >= 8) return false;
+      dp.R[dp.nst++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+DctPlan make_dct_plan(int N) {
+  DctPlan dp{};
+  dp.N = N;
+  dp.M = N / 2;
+  dp.fft = 0;
+  if (N >= 2 && N % 2 == 0 && factor_radices(N / 2, dp)) dp.fft = 1;
+  if (dp.fft) {
+    int ls = (dp.M - 1) + ((dp.M - 1) >> 4) + 1;
+    if (ls % 2 == 0) ls += 1;
+    dp.lstride = ls;  // complex slots per line
+  } else {
+    dp.nst = 0;
+    dp.lstride = (N + 1) / 2 + 1;  // complex slots holding N reals
+  }
+  return dp;
+}
+
+struct Sizes {
+  size_t off_kap_s, off_kap_hi, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
+      off_part, off_st, off_hist, total;
+  int max_partials;
+};
+
+void canonical_dims(const int64_t n[3], int axis, int& nL, int& na, int& nb) {
+  nL = (int)n[axis];
+  int o[2], c = 0;
+  for (int d = 0; d < 3; ++d)
+    if (d != axis) o[c++] = (int)n[d];
+  na = o[0];
+  nb = o[1];
+}
+
+LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt) {
+  LaunchCfg lc{};
+  const size_t cx_sz = 2 * elt;
+  // operator: aim for >= ~4096 blocks
+  const int gx = (g.nb + 63) / 64, gy = (g.na + 3) / 4;
+  const int64_t cols = (int64_t)gx * gy;
+  int kchunk = g.nL;
+  while (kchunk > 8 && cols * ((g.nL + kchunk - 1) / kchunk) < 4096) kchunk = (kchunk + 1) / 2;
+  lc.kchunk = kchunk;
+  lc.gridA = dim3(gx, gy, (g.nL + kchunk - 1) / kchunk);
+  // rows (b axis)
+  {
+    const size_t line_bytes = (size_t)dpb.lstride * cx_sz;
+    int rpb = (int)std::max<size_t>(1, (48 * 1024) / line_bytes);
+    if (dpb.fft) rpb = std::min(rpb, std::max(1, 16 * kThreads / dpb.M));
+    rpb = std::min(rpb, 64);
+    lc.nrows = g.nL * g.na;
+    rpb = std::min(rpb, lc.nrows);
+    lc.rpb = rpb;
+    lc.gridRows = (lc.nrows + rpb - 1) / rpb;
+    lc.ldsRows = (size_t)rpb * line_bytes;
+  }
+  // columns (a axis)
+  {
+    const size_t line_bytes = (size_t)dpa.lstride * cx_sz;
+    int tb = (int)std::max<size_t>(1, (64 * 1024) / line_bytes);
+    if (dpa.fft) tb = std::min(tb, std::max(1, 16 * kThreads / dpa.M));
+    tb = std::min(tb, 32);
+    if (tb >= 16) tb = 16 * (tb / 16);
+    else if (tb >= 8) tb = 8;
+    tb = std::min(tb, g.nb);
+    lc.tb = tb;
+    lc.gridCols = dim3((g.nb + tb - 1) / tb, g.nL, 1);
+    lc.ldsCols = (size_t)tb * line_bytes;
+  }
+  // tridiagonal
+  {
+    int Puse = std::max(1, std::min(kThomasP, g.nL / 2));
+    int m = (g.nL + Puse - 1) / Puse;
+    lc.Puse = Puse;
+    lc.maxm = m;
+    lc.gridThomas = dim3((g.nb + kThomasTB - 1) / kThomasTB, g.na, 1);
+  }
+  int64_t gs = (g.V + kThreads - 1) / kThreads;
+  lc.gridStride = (int)std::min<int64_t>(gs, kMaxGridStride);
+  int64_t gk = (g.plane + kThreads - 1) / kThreads;
+  lc.gridKeff = (int)std::min<int64_t>(gk, 1024);
+  return lc;
+}
+
+int max_partials_of(const LaunchCfg& lc) {
+  int64_t m = 1024;
+  m = std::max<int64_t>(m, (int64_t)lc.gridA.x * lc.gridA.y * lc.gridA.z);
+  m = std::max<int64_t>(m, lc.gridRows);
+  m = std::max<int64_t>(m, (int64_t)lc.gridThomas.x * lc.gridThomas.y);
+  m = std::max<int64_t>(m, (int64_t)lc.gridStride * 12);
+  m = std::max<int64_t>(m, (int64_t)lc.gridKeff * 2);
+  return (int)m;
+}
+
+etc_status validate(const int64_t n[3], int axis, const etc_options& o) {
+  if (!n) return fail(ETC_E_INVALID, "n is NULL");
+  if (axis < 0 || axis > 2) return fail(ETC_E_INVALID, "axis must be 0, 1 or 2");
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 1) return fail(ETC_E_INVALID, "every dimension must be >= 1");
+  if (n[axis] < 2) return fail(ETC_E_INVALID, "the load axis needs at least 2 voxels");
+  for (int d = 0; d < 3; ++d)
+    if (n[d] > (1 << 20)) return fail(ETC_E_UNSUPPORTED, "dimension too large");
+  int nL, na, nb;
+  canonical_dims(n, axis, nL, na, nb);
+  if ((int64_t)na * nb > (int64_t)1 << 31) return fail(ETC_E_UNSUPPORTED, "transverse plane too large");
+  if (na > 65535) return fail(ETC_E_UNSUPPORTED, "transverse axis a longer than 65535");
+  if (nL > kThomasP * 64) return fail(ETC_E_UNSUPPORTED, "load axis longer than 2048");
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(ETC_E_INVALID, "rtol must be > 0");
+  if (o.max_iter < 0) return fail(ETC_E_INVALID, "max_iter must be >= 0");
+  if (o.precision != ETC_FP64 && o.precision != ETC_MIXED) return fail(ETC_E_INVALID, "bad precision");
+  if (o.kref_mode == ETC_KREF_USER)
+    for (int i = 0; i < 5; ++i)
+      if (!(o.kref_user[i] > 0.0) || !std::isfinite(o.kref_user[i]))
+        return fail(ETC_E_INVALID, "kref_user entries must be finite and > 0");
+  for (int d = 0; d < 3; ++d)
+    if (o.L[d] < 0.0 || !std::isfinite(o.L[d])) return fail(ETC_E_INVALID, "L must be >= 0");
+  const bool anyL = o.L[0] != 0.0 || o.L[1] != 0.0 || o.L[2] != 0.0;
+  if (anyL && !(o.L[0] > 0.0 && o.L[1] > 0.0 && o.L[2] > 0.0))
+    return fail(ETC_E_INVALID, "L must be all zero or all positive");
+  return ETC_OK;
+}
+
+Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& o) {
+  int nL, na, nb;
+  canonical_dims(n, axis, nL, na, nb);
+  Geo g{};
+  g.nL = nL;
+  g.na = na;
+  g.nb = nb;
+  g.plane = (int64_t)na * nb;
+  g.V = g.plane * nL;
+  const size_t es = elt_size(o.precision);
+  DctPlan dpa = make_dct_plan(na), dpb = make_dct_plan(nb);
+  LaunchCfg lc = make_launch(g, dpa, dpb, es);
+  Sizes s{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o2 = off;
+    off += align_up(bytes);
+    return o2;
+  };
+  const size_t V = (size_t)g.V;
+  s.off_kap_s = take(V * es);
+  s.off_kap_hi = take((o.precision == ETC_MIXED && dt == ETC_F64) ? V * sizeof(double) : 0);
+  s.off_p = take(V * sizeof(double));
+  s.off_r = take(V * es);
+  s.off_w = take(V * es);
+  s.off_q = take(V * es);
+  s.off_t = take(V * es);
+  s.off_lam_a = take(na * sizeof(double));
+  s.off_lam_b = take(nb * sizeof(double));
+  s.off_tw_a = take((size_t)4 * na * 2 * es);
+  s.off_tw_b = take((size_t)4 * nb * 2 * es);
+  s.max_partials = max_partials_of(lc);
+  s.off_part = take((size_t)s.max_partials * sizeof(double));
+  s.off_st = take(sizeof(DevState));
+  s.off_hist = take((size_t)(o.max_iter + 2) * sizeof(double));
+  s.total = off;
+  return s;
+}
+
+template <class T> void fill_twiddles(std::vector<cx<T>>& tw, int N) {
+  tw.resize((size_t)4 * N);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < 4 * N; ++j) {
+    const long double ang = -2.0L * pi * (long double)j / (4.0L * (long double)N);
+    tw[j].re = (T)std::cos(ang);
+    tw[j].im = (T)std::sin(ang);
+  }
+}
+
+void fill_lambda(std::vector<double>& lam, int N) {
+  lam.resize(N);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < N; ++k) {
+    const long double sn = std::sin(pi * (long double)k / (2.0L * (long double)N));
+    lam[k] = (double)(4.0L * sn * sn);  // = 2 (1 - cos(k pi / N))
+  }
+}
+
+// ------------------------------------------------------------------ launches
+template <class S> struct Ops {
+  using T = S;
+
+  static etc_status canon(etc_plan* P, const void* kappa) {
+    const Geo& g = P->g;
+    S* ks = (S*)P->kap_s;
+    if (P->in_dt == ETC_F64) {
+      const double* src = (const double*)kappa;
+      if (P->axis == 2) {
+        dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+        k_canon_axis2<double, S><<<grid, dim3(32, 8), 0, P->stream>>>(src, ks, P->kap_hi, g);
+      } else {
+        k_canon_rows<double, S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(src, ks, P->kap_hi, P->axis, g);
+      }
+    } else {
+      const float* src = (const float*)kappa;
+      if (P->axis == 2) {
+        dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+        k_canon_axis2<float, S><<<grid, dim3(32, 8), 0, P->stream>>>(src, ks, P->kap_hi, g);
+      } else {
+        k_canon_rows<float, S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(src, ks, P->kap_hi, P->axis, g);
+      }
+    }
+    LAUNCHCHK("canon");
+    k_extrema<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(g, ks, P->kap_hi, P->partials);
+    LAUNCHCHK("extrema");
+    return ETC_OK;
+  }
+
+  static RefMedium ref(const etc_plan* P) {
+    RefMedium rm;
+    rm.kL = P->kref[0];
+    rm.ka = P->kref[1];
+    rm.kb = P->kref[2];
+    rm.kin = P->kref[3];
+    rm.kout = P->kref[4];
+    rm.lam_a = P->lam_a;
+    rm.lam_b = P->lam_b;
+    return rm;
+  }
+
+  static etc_status thomas(etc_plan* P, S* t, double* partials, const DevState* st, int gate) {
+    const LaunchCfg& lc = P->lc;
+    const RefMedium rm = ref(P);
+    const int threads = kThomasTB * kThomasP;
+    if (lc.maxm <= 16)
+      k_thomas<S, kThomasTB, kThomasP, 16><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+    else if (lc.maxm <= 32)
+      k_thomas<S, kThomasTB, kThomasP, 32><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+    else
+      k_thomas<S, kThomasTB, kThomasP, 64><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+    LAUNCHCHK("thomas");
+    return ETC_OK;
+  }
+
+  static etc_status fin(etc_plan* P, int op, int n) {
+    k_fin<<<1, 1024, 0, P->stream>>>(op, P->partials, n, P->st, P->hist);
+    LAUNCHCHK("finalize");
+    return ETC_OK;
+  }
+
+  static void timer_begin(etc_plan* P, int id) {
+    if (P->timer_id == id && P->ev_used + 2 <= (int)P->ev.size()) (void)hipEventRecord(P->ev[P->ev_used], P->stream);
+  }
+  static void timer_end(etc_plan* P, int id) {
+    if (P->timer_id == id && P->ev_used + 2 <= (int)P->ev.size()) {
+      (void)hipEventRecord(P->ev[P->ev_used + 1], P->stream);
+      P->ev_used += 2;
+    }
+  }
+
+  // Preconditioner of the initial pass (and of etc_apply_Minv):
+  // t = DCT_b(src); t = DCT_a(t); Thomas; t = DCT_a^{-1}(t); dst = DCT_b^{-1}(t).
+  static etc_status precond(etc_plan* P, const S* src, S* dst, int inv_mode, const DevState* st, int gate,
+                            int fin_op) {
+    const LaunchCfg& lc = P->lc;
+    S* t = (S*)P->t;
+    const cx<T>* twa = (const cx<T>*)P->tw_a;
+    const cx<T>* twb = (const cx<T>*)P->tw_b;
+    k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
+        P->g, P->dpb, twb, src, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, st, gate);
+    LAUNCHCHK("rows_fwd");
+    k_cols<S, T, -1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
+    LAUNCHCHK("cols_fwd");
+    etc_status s = thomas(P, t, P->partials, st, gate);
+    if (s) return s;
+    s = fin(P, fin_op, lc.gridThomas.x * lc.gridThomas.y);
+    if (s) return s;
+    k_cols<S, T, +1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
+    LAUNCHCHK("cols_inv");
+    if (inv_mode == 1)
+      k_rows_inv<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, t, dst, lc.rpb,
+                                                                           lc.nrows, st, gate);
+    else
+      k_rows_inv<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, t, dst, lc.rpb,
+                                                                           lc.nrows, st, gate);
+    LAUNCHCHK("rows_inv");
+    return ETC_OK;
+  }
+
+  // Initial pass: p = p0 (or 0), r = b - A p, z = M^{-1} r, w = z, rho = r.z.
+  static etc_status init(etc_plan* P, const double* p0_user) {
+    const LaunchCfg& lc = P->lc;
+    const Geo& g = P->g;
+    S* r = (S*)P->r;
+    S* w = (S*)P->w;
+    k_init<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, r, (const S*)P->kap_s, P->kap_hi, P->partials);
+    LAUNCHCHK("init");
+    etc_status s = fin(P, FIN_BNORM, lc.gridStride);
+    if (s) return s;
+    if (p0_user) {
+      // canonical copy of p0 into p (double), then r = b - A p0
+      if (P->axis == 2) {
+        dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+        k_canon_axis2<double, double><<<grid, dim3(32, 8), 0, P->stream>>>(p0_user, P->p, nullptr, g);
+      } else {
+        k_canon_rows<double, double><<<lc.gridStride, kThreads, 0, P->stream>>>(p0_user, P->p, nullptr, P->axis, g);
+      }
+      LAUNCHCHK("p0");
+      k_residual<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(g, P->p, (const S*)P->kap_s, P->kap_hi, r, P->partials,
+                                                             nullptr, 0, lc.kchunk);
+      LAUNCHCHK("residual");
+      // relative residual of the warm start
+      k_fin<<<1, 1024, 0, P->stream>>>(FIN_RR0, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
+      LAUNCHCHK("fin");
+    }
+    return precond(P, r, w, 0, P->st, 1, FIN_RHO0);
+  }
+
+  // One PCG pass (alg:pcg loop body) on the device.
+  static etc_status iteration(etc_plan* P) {
+    const LaunchCfg& lc = P->lc;
+    const Geo& g = P->g;
+    S* r = (S*)P->r;
+    S* w = (S*)P->w;
+    S* q = (S*)P->q;
+    S* t = (S*)P->t;
+    const S* ks = (const S*)P->kap_s;
+    const cx<T>* twa = (const cx<T>*)P->tw_a;
+    const cx<T>* twb = (const cx<T>*)P->tw_b;
+    etc_status s;
+    // q = A w, alpha = rho / (w . q)
+    timer_begin(P, 1);
+    k_apply_A<S, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(g, w, ks, q, P->partials, P->st, 1, lc.kchunk);
+    timer_end(P, 1);
+    LAUNCHCHK("apply_A");
+    if ((s = fin(P, FIN_ALPHA, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+    // p += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
+    timer_begin(P, 2);
+    k_rows_fwd<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(g, P->dpb, twb, nullptr, t, lc.rpb,
+                                                                         lc.nrows, P->p, w, r, q, P->partials,
+                                                                         P->st, 1);
+    timer_end(P, 2);
+    LAUNCHCHK("update_rows_fwd");
+    if ((s = fin(P, FIN_RR, lc.gridRows))) return s;
+    if (P->prec == ETC_MIXED) {
+      // replace r by the float64 true residual when requested, and redo DCT_b
+      k_residual<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(g, P->p, ks, P->kap_hi, r, P->partials, P->st, 2,
+                                                             lc.kchunk);
+      LAUNCHCHK("residual");
+      if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+      k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
+          g, P->dpb, twb, r, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
+      LAUNCHCHK("rows_fwd_refine");
+    }
+    timer_begin(P, 3);
+    k_cols<S, T, -1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
+    timer_end(P, 3);
+    LAUNCHCHK("cols_fwd");
+    timer_begin(P, 4);
+    s = thomas(P, t, P->partials, P->st, 1);
+    timer_end(P, 4);
+    if (s) return s;
+    if ((s = fin(P, FIN_BETA, lc.gridThomas.x * lc.gridThomas.y))) return s;
+    timer_begin(P, 5);
+    k_cols<S, T, +1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
+    timer_end(P, 5);
+    LAUNCHCHK("cols_inv");
+    // w = DCT_b^{-1}(t) + beta w
+    timer_begin(P, 6);
+    k_rows_inv<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(g, P->dpb, twb, t, w, lc.rpb, lc.nrows,
+                                                                         P->st, 1);
+    timer_end(P, 6);
+    LAUNCHCHK("rows_inv_dir");
+    return ETC_OK;
+  }
+
+  static etc_status keff(etc_plan* P, bool energy) {
+    const LaunchCfg& lc = P->lc;
+    const S* ks = (const S*)P->kap_s;
+    k_keff<S><<<lc.gridKeff, kThreads, 0, P->stream>>>(P->g, P->p, ks, P->kap_hi, P->partials);
+    LAUNCHCHK("keff");
+    k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC0, P->partials, lc.gridKeff, P->st, P->hist);
+    k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC1, P->partials + lc.gridKeff, lc.gridKeff, P->st, P->hist);
+    LAUNCHCHK("fin");
+    if (energy) {
+      k_energy<S><<<lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, ks, P->kap_hi, P->partials);
+      LAUNCHCHK("energy");
+      k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC2, P->partials, lc.gridStride, P->st, P->hist);
+      LAUNCHCHK("fin");
+    }
+    return ETC_OK;
+  }
+
+  static etc_status apply_A(etc_plan* P, const void* x, void* y, bool dot) {
+    const LaunchCfg& lc = P->lc;
+    k_apply_A<S, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, (const S*)x, (const S*)P->kap_s, (S*)y,
+                                                            dot ? P->partials : nullptr, nullptr, 0, lc.kchunk);
+    LAUNCHCHK("apply_A");
+    if (dot) {
+      k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC3, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
+      LAUNCHCHK("fin");
+    }
+    return ETC_OK;
+  }
+};
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+void etc_options_default(etc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = ETC_FP64;
+  o->kref_mode = ETC_KREF_MID;
+  for (int i = 0; i < 5; ++i) o->kref_user[i] = 1.0;
+  o->rtol = 1e-6;
+  o->max_iter = 1000;
+  o->refine_every = 10;
+  o->poll_every = 8;
+  o->stream = nullptr;
+}
+
+const char* etc_last_error(void) { return g_err.c_str(); }
+
+const char* etc_version(void) { return "etc-mi355x 0.1 (gfx950)"; }
+
+etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const etc_options* opt, size_t* bytes) {
+  etc_options o;
+  if (opt) o = *opt;
+  else etc_options_default(&o);
+  if (!bytes) return fail(ETC_E_INVALID, "bytes is NULL");
+  etc_status s = validate(n, axis, o);
+  if (s) return s;
+  *bytes = plan_sizes(n, axis, dt, o).total;
+  return ETC_OK;
+}
+
+etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                     const etc_options* opt, etc_plan** out) {
+  if (!out) return fail(ETC_E_INVALID, "plan is NULL");
+  *out = nullptr;
+  if (!kappa) return fail(ETC_E_INVALID, "kappa is NULL");
+  if (dt != ETC_F64 && dt != ETC_F32) return fail(ETC_E_INVALID, "bad dtype");
+  etc_options o;
+  if (opt) o = *opt;
+  else etc_options_default(&o);
+  etc_status s = validate(n, axis, o);
+  if (s) return s;
+  if (!(bc.p_in != bc.p_out) || !std::isfinite(bc.p_in) || !std::isfinite(bc.p_out))
+    return fail(ETC_E_INVALID, "p_in and p_out must be finite and differ");
+  if (o.poll_every < 1) o.poll_every = 1;
+
+  etc_plan* P = new etc_plan();
+  P->opt = o;
+  P->axis = axis;
+  P->in_dt = dt;
+  P->prec = o.precision;
+  P->stream = (hipStream_t)o.stream;
+  P->timer_id = 0;
+  P->ev_used = 0;
+  for (int d = 0; d < 3; ++d) P->n_user[d] = n[d];
+  int nL, na, nb;
+  canonical_dims(n, axis, nL, na, nb);
+  Geo& g = P->g;
+  g.nL = nL;
+  g.na = na;
+  g.nb = nb;
+  g.plane = (int64_t)na * nb;
+  g.V = g.plane * nL;
+  {
+    double h_user[3] = {1.0, 1.0, 1.0};
+    if (o.L[0] > 0.0)
+      for (int d = 0; d < 3; ++d) h_user[d] = o.L[d] / (double)n[d];
+    int order[3] = {axis, 0, 0}, c = 1;
+    for (int d = 0; d < 3; ++d)
+      if (d != axis) order[c++] = d;
+    g.fL = 1.0 / (h_user[order[0]] * h_user[order[0]]);
+    g.fa = 1.0 / (h_user[order[1]] * h_user[order[1]]);
+    g.fb = 1.0 / (h_user[order[2]] * h_user[order[2]]);
+  }
+  g.p_in = bc.p_in;
+  g.p_out = bc.p_out;
+  const size_t es = elt_size(P->prec);
+  P->dpa = make_dct_plan(na);
+  P->dpb = make_dct_plan(nb);
+  P->lc = make_launch(g, P->dpa, P->dpb, es);
+
+  Sizes sz = plan_sizes(n, axis, dt, o);
+  P->max_partials = sz.max_partials;
+  if (o.workspace) {
+    if (o.workspace_bytes < sz.total) {
+      delete P;
+      return fail(ETC_E_NOMEM, "workspace smaller than etc_workspace_size");
+    }
+    P->own_ws = false;
+    P->ws = (char*)o.workspace;
+    P->ws_bytes = o.workspace_bytes;
+  } else {
+    P->own_ws = true;
+    if (hipMalloc((void**)&P->ws, sz.total) != hipSuccess) {
+      delete P;
+      return fail(ETC_E_NOMEM, "hipMalloc of the workspace failed");
+    }
+    P->ws_bytes = sz.total;
+  }
+  if (hipHostMalloc((void**)&P->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+    if (P->own_ws) (void)hipFree(P->ws);
+    delete P;
+    return fail(ETC_E_NOMEM, "pinned host allocation failed");
+  }
+  char* b = P->ws;
+  P->kap_s = b + sz.off_kap_s;
+  P->kap_hi = (P->prec == ETC_MIXED && dt == ETC_F64) ? (double*)(b + sz.off_kap_hi) : nullptr;
+  P->p = (double*)(b + sz.off_p);
+  P->r = b + sz.off_r;
+  P->w = b + sz.off_w;
+  P->q = b + sz.off_q;
+  P->t = b + sz.off_t;
+  P->lam_a = (double*)(b + sz.off_lam_a);
+  P->lam_b = (double*)(b + sz.off_lam_b);
+  P->tw_a = b + sz.off_tw_a;
+  P->tw_b = b + sz.off_tw_b;
+  P->partials = (double*)(b + sz.off_part);
+  P->st = (DevState*)(b + sz.off_st);
+  P->hist = (double*)(b + sz.off_hist);
+
+  auto bail = [&](etc_status st) {
+    etc_destroy(P);
+    return st;
+  };
+
+  // canonical copy + extrema
+  s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, kappa) : Ops<double>::canon(P, kappa);
+  if (s) return bail(s);
+  std::vector<double> part((size_t)P->lc.gridStride * 12);
+  if (hipMemcpyAsync(part.data(), P->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(P->stream) != hipSuccess)
+    return bail(fail(ETC_E_HIP, "reading the extrema failed"));
+  double mn[5], mx[5], bad = 0.0;
+  for (int f = 0; f < 5; ++f) {
+    mn[f] = INFINITY;
+    mx[f] = -INFINITY;
+  }
+  for (int blk = 0; blk < P->lc.gridStride; ++blk) {
+    for (int f = 0; f < 5; ++f) {
+      mn[f] = std::fmin(mn[f], part[(size_t)blk * 12 + 2 * f]);
+      mx[f] = std::fmax(mx[f], part[(size_t)blk * 12 + 2 * f + 1]);
+    }
+    bad += part[(size_t)blk * 12 + 10];
+  }
+  if (bad > 0.0) return bail(fail(ETC_E_INVALID, "kappa holds values that are <= 0, NaN or Inf"));
+  for (int f = 0; f < 5; ++f) {
+    P->ext[2 * f] = mn[f];
+    P->ext[2 * f + 1] = mx[f];
+  }
+  for (int f = 0; f < 5; ++f) {
+    const bool empty = !(mn[f] <= mx[f]);
+    if (o.kref_mode == ETC_KREF_USER) P->kref[f] = o.kref_user[f];
+    else if (o.kref_mode == ETC_KREF_ONE || empty) P->kref[f] = 1.0;
+    else P->kref[f] = std::sqrt(mn[f] * mx[f]);
+  }
+  {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int f = 0; f < 5; ++f) {
+      if (!(mn[f] <= mx[f])) continue;
+      lo = std::fmin(lo, mn[f] / P->kref[f]);
+      hi = std::fmax(hi, mx[f] / P->kref[f]);
+    }
+    P->lam_lo = lo;
+    P->lam_hi = hi;
+  }
+  // tables
+  {
+    std::vector<double> la, lb;
+    fill_lambda(la, na);
+    fill_lambda(lb, nb);
+    std::vector<unsigned char> twa, twb;
+    if (P->prec == ETC_MIXED) {
+      std::vector<cx<float>> a, c;
+      fill_twiddles(a, na);
+      fill_twiddles(c, nb);
+      twa.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
+      twb.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
+    } else {
+      std::vector<cx<double>> a, c;
+      fill_twiddles(a, na);
+      fill_twiddles(c, nb);
+      twa.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
+      twb.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
+    }
+    if (hipMemcpyAsync(P->lam_a, la.data(), na * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->lam_b, lb.data(), nb * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->tw_a, twa.data(), twa.size(), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->tw_b, twb.data(), twb.size(), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess)
+      return bail(fail(ETC_E_HIP, "uploading the tables failed"));
+  }
+  P->solved = false;
+  *out = P;
+  return ETC_OK;
+}
+
+static etc_status reset_state(etc_plan* P) {
+  DevState h{};
+  h.rtol = P->opt.rtol;
+  h.max_iter = P->opt.max_iter;
+  h.refine_every = (P->prec == ETC_MIXED) ? std::max(0, P->opt.refine_every) : 0;
+  h.mixed = (P->prec == ETC_MIXED) ? 1 : 0;
+  *P->st_host = h;
+  HIPCHK(hipMemcpyAsync(P->st, P->st_host, sizeof(DevState), hipMemcpyHostToDevice, P->stream));
+  return ETC_OK;
+}
+
+etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
+  if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  etc_status s = reset_state(P);
+  if (s) return s;
+  // kernel timer events
+  if (P->timer_id > 0) {
+    const size_t need = (size_t)2 * (P->opt.max_iter + 2);
+    while (P->ev.size() < need) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      P->ev.push_back(e);
+    }
+  }
+  P->ev_used = 0;
+  s = (P->prec == ETC_MIXED) ? Ops<float>::init(P, p0) : Ops<double>::init(P, p0);
+  if (s) return s;
+  int enq = 0;
+  const int chunk = P->opt.poll_every;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    if (P->st_host->done || enq > P->opt.max_iter) break;
+    for (int i = 0; i < chunk; ++i) {
+      s = (P->prec == ETC_MIXED) ? Ops<float>::iteration(P) : Ops<double>::iteration(P);
+      if (s) return s;
+    }
+    enq += chunk;
+  }
+  const DevState& h = *P->st_host;
+  P->last_iters = h.iter;
+  P->last_status = h.done ? h.status : ETC_NOT_CONVERGED;
+  if (P->timer_id > 0) {
+    double tot = 0.0;
+    for (int i = 0; i + 1 < P->ev_used; i += 2) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
+      tot += ms;
+    }
+    P->timer_ms = tot;
+    P->timer_launches = P->ev_used / 2;
+  }
+  if (res) {
+    res->iters = h.iter;
+    res->status = P->last_status;
+    res->relres = h.relres;
+    for (int i = 0; i < 5; ++i) res->kref[i] = P->kref[i];
+    res->lambda_lo = P->lam_lo;
+    res->lambda_hi = P->lam_hi;
+  }
+  if (P->last_status == ST_BREAKDOWN) {
+    P->solved = false;
+    return fail(ETC_E_BREAKDOWN, "PCG breakdown (non-positive or non-finite scalar)");
+  }
+  P->solved = true;
+  if (P->last_status == ST_NOT_CONVERGED) {
+    g_err = "iteration cap reached";
+    return ETC_NOT_CONVERGED;
+  }
+  return ETC_OK;
+}
+
+etc_status etc_keff(etc_plan* P, double* k_out, double* k_in, double* k_energy) {
+  if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (!P->solved) return fail(ETC_E_STATE, "etc_keff before a successful etc_solve");
+  if (!k_out) return fail(ETC_E_INVALID, "k_out is NULL");
+  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::keff(P, k_energy != nullptr)
+                                        : Ops<double>::keff(P, k_energy != nullptr);
+  if (s) return s;
+  HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  const Geo& g = P->g;
+  const double dp = g.p_in - g.p_out;
+  const double scale = (double)g.nL / ((double)g.na * (double)g.nb * dp);
+  *k_out = scale * P->st_host->k_acc[0];
+  if (k_in) *k_in = scale * P->st_host->k_acc[1];
+  if (k_energy) *k_energy = scale / g.fL * P->st_host->k_acc[2] / dp;
+  return ETC_OK;
+}
+
+etc_status etc_get_solution(const etc_plan* P, double* p) {
+  if (!P || !p) return fail(ETC_E_INVALID, "NULL argument");
+  if (!P->solved) return fail(ETC_E_STATE, "etc_get_solution before a successful etc_solve");
+  const Geo& g = P->g;
+  if (P->axis == 2) {
+    dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+    k_decanon_axis2<<<grid, dim3(32, 8), 0, P->stream>>>(P->p, p, g);
+  } else {
+    k_decanon_rows<<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->p, p, P->axis, g);
+  }
+  LAUNCHCHK("decanon");
+  return ETC_OK;
+}
+
+etc_status etc_residual_history(const etc_plan* P, double* hist, int cap, int* count) {
+  if (!P || !hist || !count) return fail(ETC_E_INVALID, "NULL argument");
+  int n = std::min(cap, P->last_iters + 1);
+  if (n < 0) n = 0;
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(hist, P->hist, n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+  }
+  *count = n;
+  return ETC_OK;
+}
+
+etc_status etc_apply_A(etc_plan* P, const void* x, void* y, double* xAx) {
+  if (!P || !x || !y) return fail(ETC_E_INVALID, "NULL argument");
+  if (x == y) return fail(ETC_E_INVALID, "x and y must not alias");
+  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::apply_A(P, x, y, xAx != nullptr)
+                                        : Ops<double>::apply_A(P, x, y, xAx != nullptr);
+  if (s) return s;
+  if (xAx) {
+    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    *xAx = P->st_host->k_acc[3];
+  }
+  return ETC_OK;
+}
+
+etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
+  if (!P || !r || !z) return fail(ETC_E_INVALID, "NULL argument");
+  if (r == z) return fail(ETC_E_INVALID, "r and z must not alias");
+  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::precond(P, (const float*)r, (float*)z, 0, P->st, 0, FIN_ACC3)
+                                        : Ops<double>::precond(P, (const double*)r, (double*)z, 0, P->st, 0, FIN_ACC3);
+  if (s) return s;
+  if (rz) {
+    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    *rz = P->st_host->k_acc[3];
+  }
+  return ETC_OK;
+}
+
+etc_status etc_set_kernel_timer(etc_plan* P, int kernel_id) {
+  if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (kernel_id < 0 || kernel_id > 6) return fail(ETC_E_INVALID, "kernel_id must be 0..6");
+  P->timer_id = kernel_id;
+  return ETC_OK;
+}
+
+etc_status etc_kernel_time(const etc_plan* P, double* total_ms, int* launches) {
+  if (!P || !total_ms || !launches) return fail(ETC_E_INVALID, "NULL argument");
+  *total_ms = P->timer_ms;
+  *launches = P->timer_launches;
+  return ETC_OK;
+}
+
+etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream) {
+  if (!src || !dst || n < 0) return fail(ETC_E_INVALID, "bad copy arguments");
+  int64_t gs = std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
+  if (gs < 1) gs = 1;
+  k_copy<<<(int)gs, kThreads, 0, (hipStream_t)stream>>>(src, dst, n);
+  LAUNCHCHK("copy");
+  return ETC_OK;
+}
+
+void etc_destroy(etc_plan* P) {
+  if (!P) return;
+  (void)hipStreamSynchronize(P->stream);
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  if (P->own_ws && P->ws) (void)hipFree(P->ws);
+  if (P->st_host) (void)hipHostFree(P->st_host);
+  delete P;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Shared device/host definitions of the ETC (effective thermal conductivity)
+// library: grid geometry, device-resident solver state, block reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace etc {
+
+// Canonical layout [k][a][b]: k = load (Dirichlet) axis, slowest; b contiguous.
+struct Geo {
+  int nL, na, nb;
+  int64_t plane;      // na * nb
+  int64_t V;          // nL * na * nb
+  double fL, fa, fb;  // 1 / h^2 per canonical axis (scaled conductivity factors)
+  double p_in, p_out;
+};
+
+// Reference-medium parameters and per-mode eigenvalue tables of the
+// preconditioner (tridiagonal shift lambda_a * ka + lambda_b * kb).
+struct RefMedium {
+  double kL, ka, kb, kin, kout;
+  const double* lam_a;  // length na, 4 sin^2(pi a' / (2 na))
+  const double* lam_b;  // length nb
+};
+
+// Solver state kept in device memory so the host never waits per dot product.
+struct DevState {
+  double rho;          // r . z of the current iterate
+  double alpha, beta;  // step and direction coefficients of the current pass
+  double wq;           // w . A w
+  double rr;           // ||r||^2 of the recursively updated residual
+  double rr_true;      // ||b - A p||^2 at the last refinement (mixed form)
+  double bnorm2;       // ||b||^2
+  double relres;       // last relative residual written to the history
+  double rtol;
+  double k_acc[4];     // result accumulators (flux sums, dissipation)
+  int iter;            // completed passes (products A w)
+  int done;            // 1: every later kernel of the solve returns at once
+  int status;          // 0 ok, 1 not converged, -4 breakdown
+  int refine;          // 1: the true residual is recomputed in this pass
+  int max_iter;
+  int refine_every;    // 0: never (FP64 form)
+  int mixed;
+  int pad;
+};
+
+enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = -4 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum: fixed shuffle tree per wave, then the wave sums in
+// order.  Result valid in thread 0.  `lds` holds >= 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) lds[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) {
+    const int nw = (nthr + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += lds[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ int flat_block() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+template <class T> __device__ __forceinline__ double to_d(T v) { return static_cast<double>(v); }
+
+// Harmonic-mean face conductivity 2 k1 k2 / (k1 + k2) of two cells.
+template <class C> __device__ __forceinline__ C harm(C k1, C k2) {
+  return C(2) * k1 * k2 / (k1 + k2);
+}
+
+}  // namespace etc

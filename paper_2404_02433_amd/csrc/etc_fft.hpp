@@ -1,0 +1,293 @@
+// Batched DCT-II / DCT-III engine for lines staged in LDS (gfx950).
+//
+// Forward transform (scale 1):   X[k] = sum_n x[n] cos(pi (2n+1) k / (2N))
+// Backward transform (scale 2/N, alpha_0 = 1/2) is its exact inverse; both are
+// the 1D pair of the paper's Section "Preconditioner system solver".
+//
+// Route for even N (M = N/2): reorder x into v (even samples ascending, odd
+// samples descending), read v as M complex values z[n] = v[2n] + i v[2n+1],
+// run an M-point complex FFT (Stockham, radices 2/3/4/5/8/16, in LDS), then
+// split the half-length spectrum and rotate by exp(-i pi k / 2N).  The
+// backward transform runs the same steps in reverse.  Lengths whose half does
+// not factor into those radices (and odd N) use the O(N^2) definition.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace etc {
+
+template <class T> struct cx {
+  T re, im;
+};
+
+template <class T> __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+template <class T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by DIR * i  (DIR = -1: forward transform sign)
+template <int DIR, class T> __device__ __forceinline__ cx<T> rot_i(cx<T> a) {
+  return DIR < 0 ? cx<T>{a.im, -a.re} : cx<T>{-a.im, a.re};
+}
+
+// Stage plan of one transform length, passed by value to kernels.
+struct DctPlan {
+  int N;        // transform length
+  int M;        // N / 2 on the FFT route
+  int fft;      // 1: FFT route, 0: O(N^2) definition
+  int nst;      // number of radix stages (product of R[] = M)
+  int R[8];
+  int lstride;  // LDS stride of one line, in elements of the line buffer
+};
+
+// LDS index padding: one spare slot after every 16 complex values keeps
+// power-of-two strided accesses from landing in one bank group.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// ----------------------------------------------------------------- codelets
+template <int DIR, class T> __device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = rot_i<DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft3(cx<T>* v) {
+  const T s60 = T(0.86602540378443864676372317075294);
+  cx<T> t1 = cadd(v[1], v[2]);
+  cx<T> t2 = {v[0].re - T(0.5) * t1.re, v[0].im - T(0.5) * t1.im};
+  cx<T> t3 = cscale(rot_i<DIR>(csub(v[1], v[2])), s60);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft5(cx<T>* v) {
+  const T c1 = T(0.30901699437494742410229341718282), c2 = T(-0.80901699437494742410229341718282);
+  const T s1 = T(0.95105651629515357211643933337938), s2 = T(0.58778525229247312916870595463907);
+  cx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]), t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  cx<T> a = {v[0].re + c1 * t1.re + c2 * t2.re, v[0].im + c1 * t1.im + c2 * t2.im};
+  cx<T> b = {v[0].re + c2 * t1.re + c1 * t2.re, v[0].im + c2 * t1.im + c1 * t2.im};
+  cx<T> u = rot_i<DIR>(cx<T>{s1 * t3.re + s2 * t4.re, s1 * t3.im + s2 * t4.im});
+  cx<T> w = rot_i<DIR>(cx<T>{s2 * t3.re - s1 * t4.re, s2 * t3.im - s1 * t4.im});
+  v[0] = cadd(v[0], cadd(t1, t2));
+  v[1] = cadd(a, u);
+  v[4] = csub(a, u);
+  v[2] = cadd(b, w);
+  v[3] = csub(b, w);
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft8(cx<T>* v) {
+  const T h = T(0.70710678118654752440084436210485);
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  // o_k *= exp(DIR 2 pi i k / 8)
+  o1 = cmul(o1, cx<T>{h, T(DIR) * h});
+  o2 = rot_i<DIR>(o2);
+  o3 = cmul(o3, cx<T>{-h, T(DIR) * h});
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft16(cx<T>* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+  const T c1 = T(0.92387953251128675612818318939679), s1 = T(0.38268343236508977172845998403040);
+  const T h = T(0.70710678118654752440084436210485);
+  cx<T> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cx<T> a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+    dft4<DIR>(a0, a1, a2, a3);
+    y[n2][0] = a0;
+    y[n2][1] = a1;
+    y[n2][2] = a2;
+    y[n2][3] = a3;
+  }
+  // twiddles exp(DIR 2 pi i n2 k1 / 16), n2 k1 in {1,2,3,4,6,9}
+  const T sg = T(DIR);
+  y[1][1] = cmul(y[1][1], cx<T>{c1, sg * s1});
+  y[1][2] = cmul(y[1][2], cx<T>{h, sg * h});
+  y[1][3] = cmul(y[1][3], cx<T>{s1, sg * c1});
+  y[2][1] = cmul(y[2][1], cx<T>{h, sg * h});
+  y[2][2] = rot_i<DIR>(y[2][2]);
+  y[2][3] = cmul(y[2][3], cx<T>{-h, sg * h});
+  y[3][1] = cmul(y[3][1], cx<T>{s1, sg * c1});
+  y[3][2] = cmul(y[3][2], cx<T>{-h, sg * h});
+  y[3][3] = cmul(y[3][3], cx<T>{-c1, -sg * s1});
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+    dft4<DIR>(a0, a1, a2, a3);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+template <int R, int DIR, class T> __device__ __forceinline__ void dftR(cx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 5) dft5<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+  else dft16<DIR>(v);
+}
+
+// ------------------------------------------------------------ Stockham stage
+// One radix-R stage over `lines` lines of M complex values (LDS, padded),
+// line stride `ls` (complex units).  `tw[j]` = exp(-2 pi i j / (8M)).
+// Every thread must call it (it contains barriers).
+template <int R> struct ipt_of {
+  static constexpr int v = (R >= 16) ? 1 : (16 / R);
+};
+
+// Items per thread of a radix-R stage: a stage over `lines` lines of M points
+// fits one pass when lines * M <= 16 * nthr.  Not inlined, so each radix gets
+// its own register allocation.
+template <class T, int R, int DIR, int IPT = ipt_of<R>::v>
+__device__ __attribute__((noinline)) void fft_stage(cx<T>* buf, int lines, int ls, int M, int Ns, const cx<T>* __restrict__ tw,
+                                          int tid, int nthr) {
+  const int per_line = M / R;
+  const int items = lines * per_line;
+  const int step = M / (Ns * R);
+  cx<T> v[IPT][R];
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int it = tid + i * nthr;
+    if (it < items) {
+      const int line = it / per_line, j = it - line * per_line;
+      const cx<T>* L = buf + line * ls;
+      const int jm = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = L[lpad(j + r * per_line)];
+      if (jm != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[8 * jm * r * step];
+          if (DIR > 0) w.im = -w.im;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dftR<R, DIR>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int it = tid + i * nthr;
+    if (it < items) {
+      const int line = it / per_line, j = it - line * per_line;
+      cx<T>* L = buf + line * ls;
+      const int jm = j % Ns;
+      const int idxD = (j / Ns) * Ns * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) L[lpad(idxD + r * Ns)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// All stages of an M-point FFT on `lines` LDS lines (natural-order output).
+template <class T, int DIR>
+__device__ void lds_fft(cx<T>* buf, int lines, int ls, const DctPlan& dp, const cx<T>* __restrict__ tw, int tid,
+                        int nthr) {
+  int Ns = 1;
+  for (int s = 0; s < dp.nst; ++s) {
+    const int R = dp.R[s];
+    switch (R) {
+      case 2: fft_stage<T, 2, DIR>(buf, lines, ls, dp.M, Ns, tw, tid, nthr); break;
+      case 3: fft_stage<T, 3, DIR>(buf, lines, ls, dp.M, Ns, tw, tid, nthr); break;
+      case 4: fft_stage<T, 4, DIR>(buf, lines, ls, dp.M, Ns, tw, tid, nthr); break;
+      case 5: fft_stage<T, 5, DIR>(buf, lines, ls, dp.M, Ns, tw, tid, nthr); break;
+      case 8: fft_stage<T, 8, DIR>(buf, lines, ls, dp.M, Ns, tw, tid, nthr); break;
+      default: fft_stage<T, 16, DIR>(buf, lines, ls, dp.M, Ns, tw, tid, nthr); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Position of input sample j in the reordered sequence v (FFT route).
+__device__ __forceinline__ int dct_perm(int j, int N) { return (j & 1) ? (N - 1 - (j >> 1)) : (j >> 1); }
+
+// Real offset (in T units) of v[m] inside a padded complex line.
+__device__ __forceinline__ int vpos(int m) { return 2 * lpad(m >> 1) + (m & 1); }
+
+// Forward post-processing of one item k in [0, M/2]: from the half-length
+// spectrum Z (LDS line) produce the outputs X[k], X[N-k], X[M-k], X[M+k].
+// `emit(index, value)` stores one output.
+template <class T, class Emit>
+__device__ __forceinline__ void dct_post(const cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Emit emit) {
+  const T half = T(0.5);
+  if (k == 0) {
+    cx<T> z0 = Z[lpad(0)];
+    emit(0, z0.re + z0.im);
+    // X[M] = Re(exp(-i pi/4) (Re z0 - Im z0))
+    emit(M, (z0.re - z0.im) * tw[M].re);
+    return;
+  }
+  const int k2 = M - k;
+  cx<T> A = Z[lpad(k)], B = Z[lpad(k2)];
+  {
+    cx<T> s = cadd(A, cconj(B)), d = csub(A, cconj(B));
+    cx<T> V = csub(cscale(s, half), cscale(rot_i<+1>(cmul(tw[4 * k], d)), half));
+    cx<T> W = cmul(tw[k], V);
+    emit(k, W.re);
+    emit(N - k, -W.im);
+  }
+  if (k2 != k) {
+    cx<T> s = cadd(B, cconj(A)), d = csub(B, cconj(A));
+    cx<T> V = csub(cscale(s, half), cscale(rot_i<+1>(cmul(tw[4 * k2], d)), half));
+    cx<T> W = cmul(tw[k2], V);
+    emit(k2, W.re);
+    emit(N - k2, -W.im);
+  }
+}
+
+// Backward pre-processing of one item k in [0, M/2]: read X[k], X[N-k],
+// X[M-k], X[M+k] through `ld(index)` and write Z[k], Z[M-k] to the LDS line.
+template <class T, class Load>
+__device__ __forceinline__ void dct_pre_inv(cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Load ld) {
+  const T half = T(0.5);
+  if (k == 0) {
+    const T x0 = ld(0), xm = ld(M);
+    cx<T> V0 = {x0, T(0)};
+    // V[M] = exp(i pi/4) (X[M] - i X[M]) = sqrt(2) X[M]
+    cx<T> VM = cmul(cconj(tw[M]), cx<T>{xm, -xm});
+    cx<T> E = cscale(cadd(V0, cconj(VM)), half);
+    cx<T> O = cscale(csub(V0, cconj(VM)), half);
+    Z[lpad(0)] = cadd(E, rot_i<+1>(O));
+    return;
+  }
+  const int k2 = M - k;
+  cx<T> Vk = cmul(cconj(tw[k]), cx<T>{ld(k), -ld(N - k)});
+  cx<T> Vk2 = cmul(cconj(tw[k2]), cx<T>{ld(k2), -ld(N - k2)});
+  {
+    cx<T> E = cscale(cadd(Vk, cconj(Vk2)), half);
+    cx<T> O = cscale(cmul(cconj(tw[4 * k]), csub(Vk, cconj(Vk2))), half);
+    Z[lpad(k)] = cadd(E, rot_i<+1>(O));
+  }
+  if (k2 != k) {
+    cx<T> E = cscale(cadd(Vk2, cconj(Vk)), half);
+    cx<T> O = cscale(cmul(cconj(tw[4 * k2]), csub(Vk2, cconj(Vk))), half);
+    Z[lpad(k2)] = cadd(E, rot_i<+1>(O));
+  }
+}
+
+}  // namespace etc

@@ -1,0 +1,838 @@
+// HIP kernels of the TPFA / DCT-preconditioned CG solver (gfx950).
+//
+// Data live in the canonical layout [k][a][b] (load axis k slowest, b
+// contiguous).  S is the storage type of the iteration vectors (double for the
+// FP64 form, float for the mixed form); the solution p is always double.
+// Every reduction writes one partial per block; a one-block finalize kernel
+// sums them in a fixed order, so results are bitwise reproducible.
+#pragma once
+#include "etc_common.hpp"
+#include "etc_fft.hpp"
+
+namespace etc {
+
+// Kernels launched inside the solve loop return at once when the device state
+// says the solve is over (gate 1) or, for refinement work, when no refinement
+// was requested in this pass (gate 2).  Standalone calls pass st = nullptr.
+__device__ __forceinline__ bool gated_out(const DevState* st, int gate) {
+  if (st == nullptr || gate == 0) return false;
+  if (st->done) return true;
+  if (gate == 2 && !st->refine) return true;
+  return false;
+}
+
+__device__ __forceinline__ double kap_at(const float* ks, const double* kh, int64_t i) {
+  return kh ? kh[i] : (double)ks[i];
+}
+__device__ __forceinline__ double kap_at(const double* ks, const double* kh, int64_t i) {
+  return kh ? kh[i] : ks[i];
+}
+
+// ===================================================================== setup
+// Canonical copy of the user's array (load axis -> slowest).  user dims:
+// axis 0: (nL, na, nb); axis 1: (na, nL, nb).  Coalesced over b.
+template <class In, class S>
+__global__ void k_canon_rows(const In* __restrict__ src, S* __restrict__ dst, double* __restrict__ dst_hi, int axis,
+                             Geo g) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    const int64_t k = i / g.plane, rem = i - k * g.plane;
+    const int64_t a = rem / g.nb, b = rem - a * g.nb;
+    const int64_t si = axis == 0 ? i : (a * g.nL + k) * g.nb + b;
+    const double v = (double)src[si];
+    dst[i] = (S)v;
+    if (dst_hi) dst_hi[i] = v;
+  }
+}
+
+// axis 2: user dims (na, nb, nL); 32x32 tile transpose of (b, k) per a.
+template <class In, class S>
+__global__ void k_canon_axis2(const In* __restrict__ src, S* __restrict__ dst, double* __restrict__ dst_hi, Geo g) {
+  __shared__ double tile[32][33];
+  const int64_t a = blockIdx.z;
+  const int b0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int b = b0 + j, k = k0 + threadIdx.x;
+    if (b < g.nb && k < g.nL) tile[j][threadIdx.x] = (double)src[(a * g.nb + b) * g.nL + k];
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int k = k0 + j, b = b0 + threadIdx.x;
+    if (k < g.nL && b < g.nb) {
+      const double v = tile[threadIdx.x][j];
+      const int64_t di = ((int64_t)k * g.na + a) * g.nb + b;
+      dst[di] = (S)v;
+      if (dst_hi) dst_hi[di] = v;
+    }
+  }
+}
+
+// Inverse permutation for the solution / gradient (double -> user layout).
+__global__ void k_decanon_rows(const double* __restrict__ src, double* __restrict__ dst, int axis, Geo g) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    const int64_t k = i / g.plane, rem = i - k * g.plane;
+    const int64_t a = rem / g.nb, b = rem - a * g.nb;
+    const int64_t di = axis == 0 ? i : (a * g.nL + k) * g.nb + b;
+    dst[di] = src[i];
+  }
+}
+
+__global__ void k_decanon_axis2(const double* __restrict__ src, double* __restrict__ dst, Geo g) {
+  __shared__ double tile[32][33];
+  const int64_t a = blockIdx.z;
+  const int b0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int k = k0 + j, b = b0 + threadIdx.x;
+    if (k < g.nL && b < g.nb) tile[j][threadIdx.x] = src[((int64_t)k * g.na + a) * g.nb + b];
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int b = b0 + j, k = k0 + threadIdx.x;
+    if (b < g.nb && k < g.nL) dst[(a * g.nb + b) * g.nL + k] = tile[threadIdx.x][j];
+  }
+}
+
+// Extrema of the five coefficient families (scaled harmonic faces normal to
+// L, a, b; scaled load-axis conductivity of the first and last layers) and a
+// count of invalid conductivities (<= 0, NaN, Inf).  12 partials per block:
+// [minL maxL mina maxa minb maxb minin maxin minout maxout invalid unused].
+template <class S>
+__global__ __launch_bounds__(256) void k_extrema(Geo g, const S* __restrict__ ks, const double* __restrict__ kh,
+                                                 double* __restrict__ partials) {
+  double mn[5], mx[5];
+  for (int f = 0; f < 5; ++f) {
+    mn[f] = __builtin_huge_val();
+    mx[f] = -__builtin_huge_val();
+  }
+  double bad = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    const int64_t k = i / g.plane, rem = i - k * g.plane;
+    const int64_t a = rem / g.nb, b = rem - a * g.nb;
+    const double kc = kap_at(ks, kh, i);
+    if (!(kc > 0.0) || !isfinite(kc)) bad += 1.0;
+    if (k > 0) {
+      const double t = g.fL * harm(kc, kap_at(ks, kh, i - g.plane));
+      mn[0] = fmin(mn[0], t);
+      mx[0] = fmax(mx[0], t);
+    }
+    if (a > 0) {
+      const double t = g.fa * harm(kc, kap_at(ks, kh, i - g.nb));
+      mn[1] = fmin(mn[1], t);
+      mx[1] = fmax(mx[1], t);
+    }
+    if (b > 0) {
+      const double t = g.fb * harm(kc, kap_at(ks, kh, i - 1));
+      mn[2] = fmin(mn[2], t);
+      mx[2] = fmax(mx[2], t);
+    }
+    if (k == 0) {
+      mn[3] = fmin(mn[3], g.fL * kc);
+      mx[3] = fmax(mx[3], g.fL * kc);
+    }
+    if (k == g.nL - 1) {
+      mn[4] = fmin(mn[4], g.fL * kc);
+      mx[4] = fmax(mx[4], g.fL * kc);
+    }
+  }
+  __shared__ double red[12][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int f = 0; f < 5; ++f) {
+    double a = mn[f], b = mx[f];
+    for (int off = 32; off > 0; off >>= 1) {
+      a = fmin(a, __shfl_down(a, off, 64));
+      b = fmax(b, __shfl_down(b, off, 64));
+    }
+    if (lane == 0) {
+      red[2 * f][wid] = a;
+      red[2 * f + 1][wid] = b;
+    }
+  }
+  double c = wave_sum(bad);
+  if (lane == 0) red[10][wid] = c;
+  __syncthreads();
+  if (threadIdx.x < 11) {
+    const int q = threadIdx.x;
+    double v = red[q][0];
+    for (int w = 1; w < 4; ++w) {
+      if (q == 10) v += red[q][w];
+      else if (q & 1) v = fmax(v, red[q][w]);
+      else v = fmin(v, red[q][w]);
+    }
+    partials[(int64_t)blockIdx.x * 12 + q] = v;
+  }
+}
+
+// p = 0, r = b (2 kappa~ p_in on the first load layer, 2 kappa~ p_out on the
+// last), partial ||b||^2.
+template <class S>
+__global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* __restrict__ r,
+                                              const S* __restrict__ ks, const double* __restrict__ kh,
+                                              double* __restrict__ partials) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t last = (int64_t)(g.nL - 1) * g.plane;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    double bv = 0.0;
+    if (i < g.plane) bv = 2.0 * g.fL * kap_at(ks, kh, i) * g.p_in;
+    if (i >= last) bv = 2.0 * g.fL * kap_at(ks, kh, i) * g.p_out;
+    p[i] = 0.0;
+    const S bs = (S)bv;
+    r[i] = bs;
+    acc += (double)bs * (double)bs;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ================================================================== operator
+// q = A w (7-point TPFA stencil, harmonic-mean faces recomputed from kappa)
+// with the partial w . q of each block.  Block (64, 4) covers 64 b x 4 a
+// columns and marches along k over `kchunk` planes keeping the k-1, k, k+1
+// values in registers; lateral neighbours come through the caches.
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w, const S* __restrict__ ks,
+                                                 S* __restrict__ q, double* __restrict__ partials,
+                                                 const DevState* __restrict__ st, int gate, int kchunk) {
+  if (gated_out(st, gate)) return;
+  __shared__ double red[16];
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  const int a = blockIdx.y * 4 + threadIdx.y;
+  const int k0 = blockIdx.z * kchunk;
+  const int k1 = min(g.nL, k0 + kchunk);
+  const bool valid = (a < g.na) && (b < g.nb);
+  double acc = 0.0;
+  if (valid) {
+    const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
+    const int64_t col = (int64_t)a * g.nb + b;
+    int64_t i = (int64_t)k0 * g.plane + col;
+    C wc = (C)w[i], kc = (C)ks[i];
+    C wm = C(0), km = C(1);
+    if (k0 > 0) {
+      wm = (C)w[i - g.plane];
+      km = (C)ks[i - g.plane];
+    }
+    for (int k = k0; k < k1; ++k, i += g.plane) {
+      C wp = C(0), kp = C(1);
+      if (k + 1 < g.nL) {
+        wp = (C)w[i + g.plane];
+        kp = (C)ks[i + g.plane];
+      }
+      C qv;
+      if (k > 0) qv = fL * harm(kc, km) * (wc - wm);
+      else qv = C(2) * fL * kc * wc;
+      if (k + 1 < g.nL) qv += fL * harm(kc, kp) * (wc - wp);
+      else qv += C(2) * fL * kc * wc;
+      if (a > 0) qv += fa * harm(kc, (C)ks[i - g.nb]) * (wc - (C)w[i - g.nb]);
+      if (a + 1 < g.na) qv += fa * harm(kc, (C)ks[i + g.nb]) * (wc - (C)w[i + g.nb]);
+      if (b > 0) qv += fb * harm(kc, (C)ks[i - 1]) * (wc - (C)w[i - 1]);
+      if (b + 1 < g.nb) qv += fb * harm(kc, (C)ks[i + 1]) * (wc - (C)w[i + 1]);
+      const S qs = (S)qv;
+      q[i] = qs;
+      acc += (double)wc * (double)qs;
+      wm = wc;
+      km = kc;
+      wc = wp;
+      kc = kp;
+    }
+  }
+  if (partials) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[flat_block()] = s;
+  }
+}
+
+// r = b - A p in double arithmetic (p double, kappa at its input precision),
+// stored at S precision, with the partial ||r||^2.  Same tiling as k_apply_A.
+template <class S>
+__global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restrict__ p, const S* __restrict__ ks,
+                                                  const double* __restrict__ kh, S* __restrict__ r,
+                                                  double* __restrict__ partials, const DevState* __restrict__ st,
+                                                  int gate, int kchunk) {
+  if (gated_out(st, gate)) return;
+  __shared__ double red[16];
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  const int a = blockIdx.y * 4 + threadIdx.y;
+  const int k0 = blockIdx.z * kchunk;
+  const int k1 = min(g.nL, k0 + kchunk);
+  const bool valid = (a < g.na) && (b < g.nb);
+  double acc = 0.0;
+  if (valid) {
+    const int64_t col = (int64_t)a * g.nb + b;
+    int64_t i = (int64_t)k0 * g.plane + col;
+    double pc = p[i], kc = kap_at(ks, kh, i);
+    double pm = 0.0, km = 1.0;
+    if (k0 > 0) {
+      pm = p[i - g.plane];
+      km = kap_at(ks, kh, i - g.plane);
+    }
+    for (int k = k0; k < k1; ++k, i += g.plane) {
+      double pp = 0.0, kp = 1.0;
+      if (k + 1 < g.nL) {
+        pp = p[i + g.plane];
+        kp = kap_at(ks, kh, i + g.plane);
+      }
+      double qv = 0.0, bv = 0.0;
+      if (k > 0) qv = g.fL * harm(kc, km) * (pc - pm);
+      else {
+        qv = 2.0 * g.fL * kc * pc;
+        bv = 2.0 * g.fL * kc * g.p_in;
+      }
+      if (k + 1 < g.nL) qv += g.fL * harm(kc, kp) * (pc - pp);
+      else {
+        qv += 2.0 * g.fL * kc * pc;
+        bv += 2.0 * g.fL * kc * g.p_out;
+      }
+      if (a > 0) qv += g.fa * harm(kc, kap_at(ks, kh, i - g.nb)) * (pc - p[i - g.nb]);
+      if (a + 1 < g.na) qv += g.fa * harm(kc, kap_at(ks, kh, i + g.nb)) * (pc - p[i + g.nb]);
+      if (b > 0) qv += g.fb * harm(kc, kap_at(ks, kh, i - 1)) * (pc - p[i - 1]);
+      if (b + 1 < g.nb) qv += g.fb * harm(kc, kap_at(ks, kh, i + 1)) * (pc - p[i + 1]);
+      const S rs = (S)(bv - qv);
+      r[i] = rs;
+      acc += (double)rs * (double)rs;
+      pm = pc;
+      km = kc;
+      pc = pp;
+      kc = kp;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[flat_block()] = s;
+}
+
+// ============================================================ DCT along rows
+// Rows are the contiguous b lines; a block owns `rpb` whole rows.
+// MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): p += alpha w,
+// r -= alpha q, partial ||r||^2, t = DCT_b(r).
+template <class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
+                                                  const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
+                                                  double* __restrict__ p, const S* __restrict__ w, S* __restrict__ r,
+                                                  const S* __restrict__ q, double* __restrict__ partials,
+                                                  const DevState* __restrict__ st, int gate) {
+  if (gated_out(st, gate)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  __shared__ double red[16];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int N = dp.N;
+  const int64_t row0 = (int64_t)blockIdx.x * rpb;
+  const int lines = (int)min((int64_t)rpb, (int64_t)nrows - row0);
+  const int64_t base = row0 * N;
+  double acc = 0.0;
+  double alpha = 0.0;
+  if (MODE == 1) alpha = st->alpha;
+  const int ls = dp.lstride;
+  // load (and update) the rows into LDS, reordered for the FFT route
+  for (int e = tid; e < lines * N; e += nthr) {
+    const int line = e / N, j = e - line * N;
+    const int64_t gi = base + e;
+    T x;
+    if (MODE == 1) {
+      p[gi] = p[gi] + alpha * (double)w[gi];
+      const S rs = (S)((double)r[gi] - alpha * (double)q[gi]);
+      r[gi] = rs;
+      acc += (double)rs * (double)rs;
+      x = (T)rs;
+    } else {
+      x = (T)src[gi];
+    }
+    T* L = reinterpret_cast<T*>(buf + line * ls);
+    if (dp.fft) L[vpos(dct_perm(j, N))] = x;
+    else L[j] = x;
+  }
+  __syncthreads();
+  if (dp.fft) {
+    lds_fft<T, -1>(buf, lines, ls, dp, tw, tid, nthr);
+    const int M = dp.M, nit = M / 2 + 1;
+    for (int e = tid; e < lines * nit; e += nthr) {
+      const int line = e / nit, k = e - line * nit;
+      S* out = dst + base + (int64_t)line * N;
+      dct_post(buf + line * ls, k, N, M, tw, [&](int idx, T v) { out[idx] = (S)v; });
+    }
+  } else {
+    const int N4 = 4 * N;
+    for (int e = tid; e < lines * N; e += nthr) {
+      const int line = e / N, k = e - line * N;
+      const T* L = reinterpret_cast<const T*>(buf + line * ls);
+      T s = T(0);
+      for (int n = 0; n < N; ++n) s += L[n] * tw[((2 * n + 1) * k) % N4].re;
+      dst[base + e] = (S)s;
+    }
+  }
+  if (MODE == 1) {
+    const double s = block_sum(acc, red);
+    if (tid == 0) partials[blockIdx.x] = s;
+  }
+}
+
+// Inverse along rows.  MODE 0: dst = DCT_b^{-1}(src).  MODE 1: dst holds w on
+// entry and leaves with w = z + beta w, z = DCT_b^{-1}(src) (never stored).
+template <class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
+                                                  const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
+                                                  const DevState* __restrict__ st, int gate) {
+  if (gated_out(st, gate)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int N = dp.N;
+  const int64_t row0 = (int64_t)blockIdx.x * rpb;
+  const int lines = (int)min((int64_t)rpb, (int64_t)nrows - row0);
+  const int64_t base = row0 * N;
+  const int ls = dp.lstride;
+  double beta = 0.0;
+  if (MODE == 1) beta = st->beta;
+  if (dp.fft) {
+    const int M = dp.M, nit = M / 2 + 1;
+    for (int e = tid; e < lines * nit; e += nthr) {
+      const int line = e / nit, k = e - line * nit;
+      const S* in = src + base + (int64_t)line * N;
+      dct_pre_inv(buf + line * ls, k, N, M, tw, [&](int idx) { return (T)in[idx]; });
+    }
+    __syncthreads();
+    lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
+    const T invM = T(1) / T(M);
+    for (int e = tid; e < lines * N; e += nthr) {
+      const int line = e / N, j = e - line * N;
+      const T* L = reinterpret_cast<const T*>(buf + line * ls);
+      const T z = L[vpos(dct_perm(j, N))] * invM;
+      const int64_t gi = base + e;
+      if (MODE == 1) dst[gi] = (S)((double)z + beta * (double)dst[gi]);
+      else dst[gi] = (S)z;
+    }
+  } else {
+    for (int e = tid; e < lines * N; e += nthr) {
+      const int line = e / N, j = e - line * N;
+      T* L = reinterpret_cast<T*>(buf + line * ls);
+      L[j] = (T)src[base + e];
+    }
+    __syncthreads();
+    const int N4 = 4 * N;
+    const T sc = T(2) / T(N);
+    for (int e = tid; e < lines * N; e += nthr) {
+      const int line = e / N, n = e - line * N;
+      const T* L = reinterpret_cast<const T*>(buf + line * ls);
+      T s = T(0.5) * L[0];
+      for (int k = 1; k < N; ++k) s += L[k] * tw[((2 * n + 1) * k) % N4].re;
+      const T z = sc * s;
+      const int64_t gi = base + e;
+      if (MODE == 1) dst[gi] = (S)((double)z + beta * (double)dst[gi]);
+      else dst[gi] = (S)z;
+    }
+  }
+}
+
+// ========================================================= DCT along columns
+// Strided axis a, in place.  A block owns `tb` adjacent b columns of one
+// plane k = blockIdx.y: every LDS line is one column (length na).
+template <class S, class T, int DIR>
+__global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
+                                              int tb, const DevState* __restrict__ st, int gate) {
+  if (gated_out(st, gate)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int N = dp.N;  // = na
+  const int b0 = blockIdx.x * tb;
+  const int lines = min(tb, g.nb - b0);
+  S* pl = data + (int64_t)blockIdx.y * g.plane + b0;
+  const int ls = dp.lstride;
+  if (DIR < 0) {
+    for (int e = tid; e < lines * N; e += nthr) {
+      const int n = e / lines, c = e - n * lines;
+      const T x = (T)pl[(int64_t)n * g.nb + c];
+      T* L = reinterpret_cast<T*>(buf + c * ls);
+      if (dp.fft) L[vpos(dct_perm(n, N))] = x;
+      else L[n] = x;
+    }
+    __syncthreads();
+    if (dp.fft) {
+      lds_fft<T, -1>(buf, lines, ls, dp, tw, tid, nthr);
+      const int M = dp.M, nit = M / 2 + 1;
+      for (int e = tid; e < lines * nit; e += nthr) {
+        const int k = e / lines, c = e - k * lines;
+        dct_post(buf + c * ls, k, N, M, tw, [&](int idx, T v) { pl[(int64_t)idx * g.nb + c] = (S)v; });
+      }
+    } else {
+      const int N4 = 4 * N;
+      for (int e = tid; e < lines * N; e += nthr) {
+        const int k = e / lines, c = e - k * lines;
+        const T* L = reinterpret_cast<const T*>(buf + c * ls);
+        T s = T(0);
+        for (int n = 0; n < N; ++n) s += L[n] * tw[((2 * n + 1) * k) % N4].re;
+        pl[(int64_t)k * g.nb + c] = (S)s;
+      }
+    }
+  } else {
+    if (dp.fft) {
+      const int M = dp.M, nit = M / 2 + 1;
+      for (int e = tid; e < lines * nit; e += nthr) {
+        const int k = e / lines, c = e - k * lines;
+        dct_pre_inv(buf + c * ls, k, N, M, tw, [&](int idx) { return (T)pl[(int64_t)idx * g.nb + c]; });
+      }
+      __syncthreads();
+      lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
+      const T invM = T(1) / T(M);
+      for (int e = tid; e < lines * N; e += nthr) {
+        const int n = e / lines, c = e - n * lines;
+        const T* L = reinterpret_cast<const T*>(buf + c * ls);
+        pl[(int64_t)n * g.nb + c] = (S)(L[vpos(dct_perm(n, N))] * invM);
+      }
+    } else {
+      for (int e = tid; e < lines * N; e += nthr) {
+        const int n = e / lines, c = e - n * lines;
+        T* L = reinterpret_cast<T*>(buf + c * ls);
+        L[n] = (T)pl[(int64_t)n * g.nb + c];
+      }
+      __syncthreads();
+      const int N4 = 4 * N;
+      const T sc = T(2) / T(N);
+      for (int e = tid; e < lines * N; e += nthr) {
+        const int n = e / lines, c = e - n * lines;
+        const T* L = reinterpret_cast<const T*>(buf + c * ls);
+        T s = T(0.5) * L[0];
+        for (int k = 1; k < N; ++k) s += L[k] * tw[((2 * n + 1) * k) % N4].re;
+        pl[(int64_t)n * g.nb + c] = (S)(sc * s);
+      }
+    }
+  }
+}
+
+// =================================================================== Thomas
+// Solve T_{a',b'} z = t along k for every transverse mode (a', b'), in place,
+// with double arithmetic.  T = s I + kL tridiag(-1, 2, -1), first and last
+// diagonal entries s + kL + 2 kin and s + kL + 2 kout, s = lam_a ka + lam_b kb.
+//
+// Partitioned elimination keeps every value in registers: the block holds TB
+// adjacent modes (lines, coalesced) times P partitions of each line.  A
+// partition is `len` interior rows followed by one separator row (none for
+// the last partition).  Each thread eliminates its interior block (LU
+// pivots and UL pivots), the separators form a symmetric tridiagonal Schur
+// complement solved by one thread per line, and each thread then corrects
+// its interior rows with the two boundary responses.
+//
+// Also returns the partial of r . z: by the DCT's Parseval relation it equals
+// (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r.
+template <class S, int TB, int P, int MAXM>
+__global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
+                                                  double* __restrict__ partials, const DevState* __restrict__ st,
+                                                  int gate) {
+  if (gated_out(st, gate)) return;
+  __shared__ double sh[8][P][TB];  // yF yL m11 mmm m1m ts|c' Dsep|d' x
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  const int l = tid % TB, p = tid / TB;
+  const int bm = blockIdx.x * TB + l;  // mode b'
+  const int am = blockIdx.y;           // mode a'
+  const int nL = g.nL;
+  const int m = (nL + Puse - 1) / Puse;
+  const int Peff = (nL + m - 1) / m;
+  const bool line_ok = bm < g.nb;
+  const int start = p * m;
+  const bool active = line_ok && p < Peff;
+  const bool has_right = active && (p < Peff - 1);
+  const int endp = min(start + m, nL);
+  const int len = active ? (endp - start - (has_right ? 1 : 0)) : 0;
+  const double kL = rm.kL;
+  const double s = line_ok ? (rm.lam_a[am] * rm.ka + rm.lam_b[bm] * rm.kb) : 0.0;
+  const double aoff = -kL;
+  const double a2 = kL * kL;
+  const double Dint = s + 2.0 * kL, D0 = s + kL + 2.0 * rm.kin, DN = s + kL + 2.0 * rm.kout;
+  auto Dof = [&](int k) { return k == 0 ? D0 : (k == nL - 1 ? DN : Dint); };
+
+  const int64_t col = (int64_t)am * g.nb + bm;
+  // register arrays are only ever indexed by unrolled constants
+  double y[MAXM], invu[MAXM], invv[MAXM];
+  double quad = 0.0, ts = 0.0, invu_last = 0.0, y_last = 0.0;
+  if (active) {
+    // forward elimination (LU), d' kept in y; t^T M^{-1} t = sum_j d'_j f_j
+    double prod = 1.0;
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j) {
+      if (j < len) {
+        const double tv = (double)t[(int64_t)(start + j) * g.plane + col];
+        double u, f;
+        if (j == 0) {
+          u = Dof(start);
+          f = tv;
+        } else {
+          u = Dof(start + j) - a2 * invu[j - 1];
+          f = tv - aoff * y[j - 1];
+          prod *= -(aoff * invu[j - 1]);
+        }
+        invu[j] = 1.0 / u;
+        y[j] = f * invu[j];
+        quad += y[j] * f;
+        if (j == len - 1) {
+          invu_last = invu[j];
+          y_last = y[j];
+        }
+      }
+    }
+    if (has_right) ts = (double)t[(int64_t)(endp - 1) * g.plane + col];
+    // back substitution y_j = d'_j - c'_j y_{j+1}, c'_j = aoff invu_j
+#pragma unroll
+    for (int j = MAXM - 2; j >= 0; --j)
+      if (j < len - 1) y[j] -= aoff * invu[j] * y[j + 1];
+    // UL pivots (bottom-up): first column of M^{-1}
+    double vprev = 0.0;
+#pragma unroll
+    for (int j = MAXM - 1; j >= 0; --j) {
+      if (j < len) {
+        double v = Dof(start + j);
+        if (j < len - 1) v -= a2 * vprev;
+        invv[j] = 1.0 / v;
+        vprev = invv[j];
+      }
+    }
+    sh[0][p][l] = y[0];
+    sh[1][p][l] = y_last;
+    sh[2][p][l] = invv[0];
+    sh[3][p][l] = invu_last;
+    sh[4][p][l] = prod * invu_last;  // (M^{-1})_{1,len}
+    sh[5][p][l] = ts;
+    sh[6][p][l] = has_right ? Dof(endp - 1) : 0.0;
+  }
+  __syncthreads();
+  // separator system (Schur complement, symmetric tridiagonal), one thread per line
+  if (p == 0 && line_ok && Peff > 1) {
+    const int nsep = Peff - 1;
+    double cprev = 0.0, dprev = 0.0;
+    for (int qd = 0; qd < nsep; ++qd) {
+      const double Lq = (qd > 0) ? -a2 * sh[4][qd][l] : 0.0;
+      const double Bq = sh[6][qd][l] - a2 * (sh[3][qd][l] + sh[2][qd + 1][l]);
+      const double Uq = (qd + 1 < nsep) ? -a2 * sh[4][qd + 1][l] : 0.0;
+      const double rq = sh[5][qd][l] - aoff * sh[1][qd][l] - aoff * sh[0][qd + 1][l];
+      const double den = Bq - Lq * cprev;
+      cprev = Uq / den;
+      dprev = (rq - Lq * dprev) / den;
+      sh[5][qd][l] = cprev;
+      sh[6][qd][l] = dprev;
+    }
+    double x = sh[6][nsep - 1][l];
+    sh[7][nsep - 1][l] = x;
+    for (int qd = nsep - 2; qd >= 0; --qd) {
+      x = sh[6][qd][l] - sh[5][qd][l] * x;
+      sh[7][qd][l] = x;
+    }
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if (active) {
+    const double zl = (p > 0) ? sh[7][p - 1][l] : 0.0;
+    const double zr = has_right ? sh[7][p][l] : 0.0;
+    const double c1 = -aoff * zl, cm = -aoff * zr;
+    const double yF = y[0], yL = y_last;
+    // add c1 M^{-1} e_1 (forward recurrence on the UL pivots)
+    double x1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j) {
+      if (j < len) {
+        x1 = (j == 0) ? invv[0] : (-aoff * invv[j] * x1);
+        y[j] += c1 * x1;
+      }
+    }
+    // add cm M^{-1} e_len (backward recurrence on the LU pivots)
+    double xm = 0.0;
+#pragma unroll
+    for (int j = MAXM - 1; j >= 0; --j) {
+      if (j < len) {
+        xm = (j == len - 1) ? invu_last : (-aoff * invu[j] * xm);
+        y[j] += cm * xm;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j)
+      if (j < len) t[(int64_t)(start + j) * g.plane + col] = (S)y[j];
+    if (has_right) t[(int64_t)(endp - 1) * g.plane + col] = (S)zr;
+    const double wa = (am == 0) ? 0.5 : 1.0, wb = (bm == 0) ? 0.5 : 1.0;
+    acc = wa * wb * (quad + c1 * yF + cm * yL + (has_right ? ts * zr : 0.0));
+  }
+  if (partials) {
+    const double sum = block_sum(acc, red);
+    if (tid == 0) partials[blockIdx.x + gridDim.x * blockIdx.y] = sum * (4.0 / ((double)g.na * (double)g.nb));
+  }
+}
+
+// ================================================================ finalize
+enum FinOp { FIN_BNORM = 0, FIN_RHO0, FIN_ALPHA, FIN_RR, FIN_REFINE, FIN_BETA, FIN_RR0, FIN_ACC0, FIN_ACC1, FIN_ACC2, FIN_ACC3 };
+
+// One block of 1024 threads sums n partials in a fixed order and applies the
+// scalar step of the iteration to the device state.
+__global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__ partials, int n, DevState* st,
+                                              double* __restrict__ hist) {
+  __shared__ double red[16];
+  if (op == FIN_REFINE) {
+    if (st->done || !st->refine) return;
+  } else if (op == FIN_ALPHA || op == FIN_RR || op == FIN_BETA || op == FIN_RHO0) {
+    if (st->done) return;
+  }
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case FIN_BNORM: {
+      st->bnorm2 = s;
+      st->rr = s;
+      st->relres = 1.0;
+      hist[0] = 1.0;
+      if (!(s > 0.0) || !isfinite(s)) {
+        st->done = 1;
+        st->status = ST_BREAKDOWN;
+      } else if (st->rtol >= 1.0) {
+        st->done = 1;
+      }
+      break;
+    }
+    case FIN_RHO0: {
+      st->rho = s;
+      if (!(s > 0.0) || !isfinite(s)) {
+        st->done = 1;
+        st->status = ST_BREAKDOWN;
+      } else if (st->max_iter <= 0) {
+        st->done = 1;
+        st->status = ST_NOT_CONVERGED;
+      }
+      break;
+    }
+    case FIN_RR0: {
+      // residual of a warm start p0
+      st->rr = s;
+      const double rel = sqrt(s / st->bnorm2);
+      st->relres = rel;
+      hist[0] = rel;
+      if (rel <= st->rtol) st->done = 1;
+      break;
+    }
+    case FIN_ALPHA: {
+      st->wq = s;
+      if (!(s > 0.0) || !isfinite(s)) {
+        st->done = 1;
+        st->status = ST_BREAKDOWN;
+      } else {
+        st->alpha = st->rho / s;
+      }
+      break;
+    }
+    case FIN_RR: {
+      st->rr = s;
+      const int it = st->iter + 1;
+      st->iter = it;
+      const double rel = sqrt(s / st->bnorm2);
+      st->relres = rel;
+      hist[it] = rel;
+      if (!isfinite(rel)) {
+        st->done = 1;
+        st->status = ST_BREAKDOWN;
+        break;
+      }
+      const bool conv = rel <= st->rtol;
+      if (!st->mixed) {
+        if (conv) {
+          st->done = 1;
+          st->status = ST_OK;
+        } else if (it >= st->max_iter) {
+          st->done = 1;
+          st->status = ST_NOT_CONVERGED;
+        }
+      } else {
+        st->refine = (conv || it >= st->max_iter || (st->refine_every > 0 && it % st->refine_every == 0)) ? 1 : 0;
+      }
+      break;
+    }
+    case FIN_REFINE: {
+      st->rr_true = s;
+      const double rel = sqrt(s / st->bnorm2);
+      st->relres = rel;
+      hist[st->iter] = rel;
+      if (rel <= st->rtol) {
+        st->done = 1;
+        st->status = ST_OK;
+      } else if (st->iter >= st->max_iter || !isfinite(rel)) {
+        st->done = 1;
+        st->status = isfinite(rel) ? ST_NOT_CONVERGED : ST_BREAKDOWN;
+      }
+      break;
+    }
+    case FIN_BETA: {
+      if (!(s > 0.0) || !isfinite(s)) {
+        st->done = 1;
+        st->status = ST_BREAKDOWN;
+      } else {
+        st->beta = s / st->rho;
+        st->rho = s;
+      }
+      break;
+    }
+    default: st->k_acc[op - FIN_ACC0] = s; break;
+  }
+}
+
+// ===================================================================== K_eff
+// Flux sums over the two Dirichlet layers: comp 0 = sum 2 kappa (p_last -
+// p_out), comp 1 = sum 2 kappa (p_in - p_first).  Partials [2][nblk].
+template <class S>
+__global__ __launch_bounds__(256) void k_keff(Geo g, const double* __restrict__ p, const S* __restrict__ ks,
+                                              const double* __restrict__ kh, double* __restrict__ partials) {
+  __shared__ double red[16];
+  double ao = 0.0, ai = 0.0;
+  const int64_t last = (int64_t)(g.nL - 1) * g.plane;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.plane; i += (int64_t)gridDim.x * blockDim.x) {
+    ao += 2.0 * kap_at(ks, kh, last + i) * (p[last + i] - g.p_out);
+    ai += 2.0 * kap_at(ks, kh, i) * (g.p_in - p[i]);
+  }
+  const double so = block_sum(ao, red);
+  const double si = block_sum(ai, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = so;
+    partials[gridDim.x + blockIdx.x] = si;
+  }
+}
+
+// Dissipation sum over every face (internal faces counted once from their
+// upper cell, plus the Dirichlet faces), double arithmetic.
+template <class S>
+__global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict__ p, const S* __restrict__ ks,
+                                                const double* __restrict__ kh, double* __restrict__ partials) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    const int64_t k = i / g.plane, rem = i - k * g.plane;
+    const int64_t a = rem / g.nb, b = rem - a * g.nb;
+    const double kc = kap_at(ks, kh, i), pc = p[i];
+    if (k > 0) {
+      const double d = pc - p[i - g.plane];
+      acc += g.fL * harm(kc, kap_at(ks, kh, i - g.plane)) * d * d;
+    } else {
+      const double d = pc - g.p_in;
+      acc += 2.0 * g.fL * kc * d * d;
+    }
+    if (k == g.nL - 1) {
+      const double d = pc - g.p_out;
+      acc += 2.0 * g.fL * kc * d * d;
+    }
+    if (a > 0) {
+      const double d = pc - p[i - g.nb];
+      acc += g.fa * harm(kc, kap_at(ks, kh, i - g.nb)) * d * d;
+    }
+    if (b > 0) {
+      const double d = pc - p[i - 1];
+      acc += g.fb * harm(kc, kap_at(ks, kh, i - 1)) * d * d;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Plain copy (bandwidth calibration of the hardware byte counters).
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace etc

@@ -1,0 +1,93 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every entry point that include/etc.h declares,
+and reject bad arguments before touching the device.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2404_02433_amd as etc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "etc.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(etc_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = etc.load_library()
+    names = declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding wraps every exported entry point with the same name
+    for name in names:
+        assert name in etc._SYMBOLS, name
+
+
+def test_version_and_defaults():
+    assert "gfx950" in etc.etc_version()
+    o = etc._options()
+    assert o.rtol == 1e-6 and o.max_iter == 1000 and o.refine_every == 10
+    assert o.precision == 0 and o.kref_mode == 0
+
+
+def test_workspace_size_scales_with_precision():
+    b64 = etc.etc_workspace_size((64, 64, 64), "float64", 0)
+    b32 = etc.etc_workspace_size((64, 64, 64), "float64", 0, precision="mixed")
+    V = 64 ** 3
+    # FP64: kappa, p, r, w, q, t = 6 doubles per voxel (+ tables)
+    assert 48 * V <= b64 < 49 * V
+    # mixed with float64 input: kappa32, kappa64, p64, r, w, q, t (float32)
+    assert 36 * V <= b32 < 37 * V
+    b32in = etc.etc_workspace_size((64, 64, 64), "float32", 0, precision="mixed")
+    assert 28 * V <= b32in < 29 * V
+
+
+@pytest.mark.parametrize("shape,axis", [((0, 4, 4), 0), ((1, 4, 4), 0), ((4, 4, 4), 3), ((4, 1, 4), 1),
+                                        ((4, 4, 4000), 2)])
+def test_workspace_size_rejects_bad_shapes(shape, axis):
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_workspace_size(shape, "float64", axis)
+    assert e.value.status in (-1, -6)
+
+
+def test_setup_rejects_bad_arguments_without_device():
+    lib = etc.load_library()
+    n = (ctypes.c_int64 * 3)(4, 4, 4)
+    o = etc._options()
+    h = ctypes.c_void_p(0)
+    # NULL kappa
+    assert lib.etc_setup(None, 0, n, etc._BC(1.0, 0.0), 0, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert "kappa" in etc.etc_last_error()
+    # p_in == p_out: no potential drop, K_eff undefined
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.etc_setup(fake, 0, n, etc._BC(1.0, 1.0), 0, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert "p_in" in etc.etc_last_error()
+    # bad axis, bad rtol, bad dtype
+    assert lib.etc_setup(fake, 0, n, etc._BC(1.0, 0.0), 5, ctypes.byref(o), ctypes.byref(h)) == -1
+    o.rtol = 0.0
+    assert lib.etc_setup(fake, 0, n, etc._BC(1.0, 0.0), 0, ctypes.byref(o), ctypes.byref(h)) == -1
+    o = etc._options()
+    assert lib.etc_setup(fake, 7, n, etc._BC(1.0, 0.0), 0, ctypes.byref(o), ctypes.byref(h)) == -1
+    # mixed-sign domain lengths
+    o = etc._options(L=(1.0, 0.0, 1.0))
+    assert lib.etc_setup(fake, 0, n, etc._BC(1.0, 0.0), 0, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert h.value in (None, 0)
+
+
+def test_state_errors_on_null_plan():
+    lib = etc.load_library()
+    d = ctypes.c_double()
+    assert lib.etc_keff(None, ctypes.byref(d), None, None) == -1
+    assert lib.etc_solve(None, None, None) == -1
+    assert lib.etc_set_kernel_timer(None, 1) == -1
+    lib.etc_destroy(None)  # no-op

@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Element-by-element comparisons on seeded inputs at sizes the oracle finishes
+in seconds, chosen to span several tiles and ragged tails (b not a multiple
+of 64, a not a multiple of 4, k chunks, FFT lengths with radices 2-16, 3 and
+5, and the O(N^2) route for odd or prime lengths).
+
+Tolerances: float64 results within a few ulps times the problem's own
+rounding growth (DCTs of length N lose ~log2(N) ulps; the tridiagonal
+solves' condition number is O(nL^2)); mixed-precision results against the
+float64 oracle within the 1e-5 relative K_eff target.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import rvegen
+from oracle import etc_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+etc = pytest.importorskip("paper_2404_02433_amd")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda:0")
+
+
+def lognormal(shape, seed, sigma=1.0):
+    rng = np.random.default_rng(seed)
+    return np.exp(sigma * rng.standard_normal(shape))
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("shape,axis", [((37, 29, 70), 0), ((12, 17, 9), 1), ((20, 8, 33), 2), ((2, 1, 1), 0)])
+def test_operator_matches_oracle_fp64(shape, axis):
+    kap = lognormal(shape, seed=sum(shape))
+    plan = etc.etc_setup(dev(kap), axis)
+    pb = O.make_problem(kap, axis)
+    x = np.random.default_rng(1).standard_normal(pb.shape)
+    y, d = etc.etc_apply_A(plan, dev(x), want_dot=True)
+    ref = O.apply_A(pb, x)
+    err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-13, err
+    assert abs(d - float(np.vdot(x, ref))) < 1e-12 * abs(float(np.vdot(x, ref)))
+    plan.close()
+
+
+def test_operator_matches_oracle_mixed():
+    shape = (33, 21, 66)
+    kap = rvegen.random_two_phase(shape, seed=4, kappa=(1.0, 100.0))
+    plan = etc.etc_setup(dev(kap), 0, precision="mixed")
+    pb = O.make_problem(kap, 0)
+    x = np.random.default_rng(2).standard_normal(pb.shape).astype(np.float32)
+    y = etc.etc_apply_A(plan, dev(x, torch.float32))
+    ref = O.apply_A(pb, x.astype(np.float64))
+    err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 2e-6, err
+    plan.close()
+
+
+# ------------------------------------------------------------ preconditioner
+PRECOND_SHAPES = [
+    (16, 32, 64),    # radices 16, 16x2
+    (10, 48, 40),    # 48 -> M=24 (8x3); 40 -> M=20 (4x5)
+    (9, 7, 12),      # odd a: O(N^2) route; 12 -> M=6 (2x3)
+    (8, 1, 5),       # a of length 1; b odd
+    (6, 80, 2),      # 80 -> M=40 (8x5); b=2 -> M=1
+    (5, 96, 160),    # 96 -> M=48 (16x3); 160 -> M=80 (16x5)
+    (64, 128, 34),   # 128 -> 16x4; 34 -> M=17 prime: O(N^2) route; nL=64: 32 partitions of 2
+    (33, 16, 16),    # nL not a multiple of the partition length
+]
+
+
+@pytest.mark.parametrize("shape", PRECOND_SHAPES)
+def test_preconditioner_matches_oracle_fp64(shape):
+    kap = lognormal(shape, seed=3 + sum(shape), sigma=0.7)
+    plan = etc.etc_setup(dev(kap), 0)
+    pb = O.make_problem(kap, 0)
+    kref = O.kref_mid(pb)
+    r = np.random.default_rng(5).standard_normal(pb.shape)
+    z, rz = etc.etc_apply_Minv(plan, dev(r), want_dot=True)
+    ref = O.apply_Aref_inv(r, kref)
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+    assert abs(rz - float(np.vdot(r, ref))) < 1e-10 * abs(float(np.vdot(r, ref)))
+    plan.close()
+
+
+def test_preconditioner_mixed_close_to_oracle():
+    shape = (32, 64, 96)
+    kap = lognormal(shape, seed=8)
+    plan = etc.etc_setup(dev(kap, torch.float32), 0, precision="mixed")
+    pb = O.make_problem(kap.astype(np.float32).astype(np.float64), 0)
+    r = np.random.default_rng(6).standard_normal(pb.shape).astype(np.float32)
+    z = etc.etc_apply_Minv(plan, dev(r, torch.float32))
+    ref = O.apply_Aref_inv(r.astype(np.float64), O.kref_mid(pb))
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
+    plan.close()
+
+
+# --------------------------------------------------------------------- solve
+def test_spheres32_fp64_trajectory_and_keff():
+    """32^3 two-phase RVE (12 spheres of radius 4, kappa 1/10), rtol 1e-10:
+    same iteration count and residual history as the oracle's PCG and K_eff
+    within 1e-9."""
+    kap, info = rvegen.make_config("spheres32")
+    ref = O.solve(kap, 0, rtol=1e-10)
+    plan = etc.etc_setup(dev(kap), 0, rtol=1e-10)
+    out = etc.etc_solve(plan)
+    k = etc.etc_keff(plan, energy=True)
+    assert out["status"] == "ok"
+    assert abs(out["iters"] - ref["iters"]) <= 1
+    assert abs(k["keff"] - ref["keff"]) <= 1e-9 * ref["keff"]
+    assert abs(k["k_in"] - ref["k_in"]) <= 1e-9 * ref["keff"]
+    assert abs(k["k_energy"] - ref["k_energy"]) <= 1e-9 * ref["keff"]
+    hist = etc.etc_residual_history(plan)
+    oh = ref["pcg"].history
+    n = min(len(hist), len(oh), 12)
+    np.testing.assert_allclose(hist[:n], oh[:n], rtol=1e-7)
+    for i, v in enumerate(out["kref"]):
+        assert abs(v - ref["kref"][O.FAMILIES[i]]) <= 1e-14 * v
+    plan.close()
+
+
+def test_mixed_keff_within_1e5_of_fp64_truth():
+    kap, _ = rvegen.make_config("spheres32")
+    truth = O.solve(kap, 0, rtol=1e-12)["keff"]
+    for dt in (torch.float64, torch.float32):
+        out = etc.solve(dev(kap, dt), 0, precision="mixed", rtol=1e-6)
+        assert out["status"] == "ok"
+        assert abs(out["keff"] - truth) <= 1e-5 * truth, (dt, out["keff"], truth)
+        assert out["relres"] <= 1e-6
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_axes_and_solution_layout(axis):
+    shape = (14, 11, 19)
+    kap = rvegen.random_two_phase(shape, seed=10 + axis, kappa=(1.0, 20.0))
+    ref = O.solve(kap, axis, p_in=2.0, p_out=-1.0, rtol=1e-11)
+    plan = etc.etc_setup(dev(kap), axis, p_in=2.0, p_out=-1.0, rtol=1e-11)
+    etc.etc_solve(plan)
+    k = etc.etc_keff(plan)
+    assert abs(k["keff"] - ref["keff"]) <= 1e-9 * ref["keff"]
+    p = etc.etc_get_solution(plan).cpu().numpy()
+    pref = O.decanonical(ref["pcg"].p, axis)
+    assert np.abs(p - pref).max() < 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 4), (6, 1, 1), (5, 1, 7), (3, 2, 1), (2, 1, 1)])
+def test_degenerate_shapes(shape):
+    kap = rvegen.random_two_phase(shape, seed=1, kappa=(0.5, 4.0))
+    ref = O.solve(kap, 0, rtol=1e-13)
+    out = etc.solve(dev(kap), 0, rtol=1e-13)
+    assert abs(out["keff"] - ref["keff"]) <= 1e-11 * ref["keff"]
+
+
+def test_homogeneous_is_exact_in_one_pass():
+    kap = np.full((24, 20, 18), 3.7)
+    out = etc.solve(dev(kap), 0, rtol=1e-12, L=(2.0, 1.0, 0.5), p_in=5.0, p_out=1.0)
+    assert out["iters"] == 1
+    assert abs(out["keff"] - 3.7) < 1e-11
+
+
+def test_laminates_on_gpu():
+    layers = 10 ** np.random.default_rng(3).uniform(-2, 2, size=40)
+    kap = rvegen.series_laminate((40, 16, 24), layers, 0)
+    out = etc.solve(dev(kap), 0, rtol=1e-13)
+    harm = len(layers) / np.sum(1 / layers)
+    assert abs(out["keff"] - harm) < 1e-10 * harm
+    plane = 10 ** np.random.default_rng(4).uniform(-2, 2, size=(16, 24))
+    kap = rvegen.parallel_laminate((40, 16, 24), plane, 0)
+    out = etc.solve(dev(kap), 0, rtol=1e-13)
+    assert abs(out["keff"] - plane.mean()) < 1e-10 * plane.mean()
+
+
+def test_invalid_conductivity_rejected():
+    kap = np.ones((8, 8, 8))
+    kap[3, 4, 5] = 0.0
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_setup(dev(kap), 0)
+    assert e.value.status == -1
+    kap[3, 4, 5] = np.nan
+    with pytest.raises(etc.EtcError):
+        etc.etc_setup(dev(kap), 0)
+
+
+def test_iteration_cap_reports_not_converged():
+    kap, _ = rvegen.make_config("spheres32")
+    plan = etc.etc_setup(dev(kap), 0, rtol=1e-12, max_iter=3)
+    out = etc.etc_solve(plan)
+    assert out["status"] == "not_converged" and out["iters"] == 3
+    ref = O.pcg(O.make_problem(kap, 0), rtol=1e-12, max_iter=3)
+    k = etc.etc_keff(plan)
+    assert abs(k["keff"] - O.keff(O.make_problem(kap, 0), ref.p)["out"]) < 1e-9
+    plan.close()
+
+
+def test_bitwise_deterministic():
+    kap = lognormal((40, 36, 52), seed=12)
+    outs = []
+    for _ in range(2):
+        plan = etc.etc_setup(dev(kap), 0, rtol=1e-9)
+        etc.etc_solve(plan)
+        outs.append(etc.etc_get_solution(plan).cpu().numpy())
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_warm_start_resume():
+    kap = lognormal((30, 28, 26), seed=13)
+    plan = etc.etc_setup(dev(kap), 0, rtol=1e-3)
+    etc.etc_solve(plan)
+    p_mid = etc.etc_get_solution(plan)
+    plan.close()
+    plan = etc.etc_setup(dev(kap), 0, rtol=1e-10)
+    out = etc.etc_solve(plan, p0=p_mid)
+    k_resumed = etc.etc_keff(plan)["keff"]
+    plan.close()
+    direct = etc.solve(dev(kap), 0, rtol=1e-10)["keff"]
+    assert out["status"] == "ok"
+    assert abs(k_resumed - direct) < 1e-8 * direct
