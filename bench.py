@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--kernel", type=int, default=2, help="hot kernel timed with HIP events (1-6)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run the plain copy kernel on MIB MiB (5 launches) and exit; the byte counters "
+                         "of this run calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note"}))
@@ -152,6 +155,16 @@ def main():
 
     import paper_2404_02433_amd as etc
     import rvegen
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            etc.etc_copy_f64(src, dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": n * 8, "copy_calib_bytes_written": n * 8, "launches": 5}))
+        return
 
     print(f"bench: generating spheres512 at n={args.n}", file=sys.stderr, flush=True)
     kap_np, info = rvegen.make_config("spheres512", args.n)

@@ -85,6 +85,7 @@ typedef struct {
   double L[3];           /* domain length per user axis; all 0 = voxel edge 1 */
   void* workspace;       /* optional caller-owned device memory (>= etc_workspace_size) */
   size_t workspace_bytes;
+  int want_grad;         /* 1: reserve the adjoint state for etc_grad (8 bytes per voxel) */
 } etc_options;
 
 typedef struct {
@@ -132,6 +133,19 @@ etc_status etc_solve(etc_plan* plan, const double* p0, etc_result* res);
  *   k_energy : from the discrete dissipation (nullable; one extra pass).
  * ETC_E_STATE before a solve. */
 etc_status etc_keff(etc_plan* plan, double* k_out, double* k_in, double* k_energy);
+
+/* Gradient dK_out/dkappa for every voxel after etc_solve, by the adjoint
+ * method: K_out depends on kappa directly and through p, and A p = b.  The
+ * adjoint state lambda solves A lambda = dK_out/dp, which is the primal system
+ * with Dirichlet pair (0, 1) scaled by nL / (na nb (p_in - p_out) fL); it is
+ * solved by a second PCG with the same plan, rtol and preconditioner.  Then
+ * dK/dkappa_v = dK/dkappa_v|_p - lambda . (dA/dkappa_v p - db/dkappa_v), a
+ * sum over the faces of voxel v of the face-coefficient derivative times the
+ * primal and adjoint jumps (harmonic-mean faces, eq:scaled bilinear forms),
+ * plus the Dirichlet-face terms.
+ *   dk_dkappa : device, user layout, float64, caller-owned.
+ * Needs a plan made with want_grad = 1 (else ETC_E_STATE).  Synchronises. */
+etc_status etc_grad(etc_plan* plan, double* dk_dkappa);
 
 /* Copy the solution p into `p` (device, user layout, float64, caller-owned). */
 etc_status etc_get_solution(const etc_plan* plan, double* p);

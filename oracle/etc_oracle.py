@@ -55,28 +55,56 @@ def decanonical(x: np.ndarray, axis: int) -> np.ndarray:
 
 @dataclass
 class Problem:
-    """Canonical TPFA problem: kappa[k, a, b], voxel edges, Dirichlet pair."""
+    """Canonical TPFA problem: kappa[k, a, b], voxel edges, Dirichlet data.
+
+    ``kap`` is the isotropic conductivity, or the load-axis component of an
+    orthotropic one when ``kap_a`` / ``kap_b`` (components along the two
+    transverse axes) are given (Section "Model problem": K = diag(kappa^x,
+    kappa^y, kappa^z) per voxel).  ``p_in`` / ``p_out`` are constants or
+    per-face arrays (na, nb) sampled at the Dirichlet face centres; ``src`` is
+    an optional volume source f sampled at cell centres."""
     kap: np.ndarray            # (nL, na, nb) float64, > 0
     h: tuple                   # voxel edge per canonical axis (hL, ha, hb)
-    p_in: float = 1.0
-    p_out: float = 0.0
+    p_in: object = 1.0
+    p_out: object = 0.0
+    kap_a: np.ndarray = None
+    kap_b: np.ndarray = None
+    src: np.ndarray = None
 
     @property
     def shape(self):
         return self.kap.shape
 
+    @property
+    def kapA(self):
+        return self.kap if self.kap_a is None else self.kap_a
 
-def make_problem(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, L=None) -> Problem:
-    """Canonicalise a user-layout array.  ``L`` = domain lengths per user axis
-    (default: cubic voxels of edge 1)."""
-    kap = canonical(kappa, axis)
-    n_user = np.asarray(kappa).shape
+    @property
+    def kapB(self):
+        return self.kap if self.kap_b is None else self.kap_b
+
+
+def make_problem(kappa, axis: int = 0, p_in=1.0, p_out=0.0, L=None, components=None, source=None) -> Problem:
+    """Canonicalise user-layout data.  ``L`` = domain lengths per user axis
+    (default: cubic voxels of edge 1).  ``components`` = three arrays, the
+    conductivity along user axes 0, 1, 2 (orthotropic K; ``kappa`` is then
+    ignored).  ``p_in`` / ``p_out`` may be arrays over the two transverse user
+    axes (in their user order); ``source`` a user-layout array."""
+    order = [axis] + [d for d in range(3) if d != axis]
+    if components is not None:
+        comps = [canonical(c, axis) for c in components]
+        kap, kap_a, kap_b = comps[order[0]], comps[order[1]], comps[order[2]]
+        n_user = np.asarray(components[0]).shape
+    else:
+        kap, kap_a, kap_b = canonical(kappa, axis), None, None
+        n_user = np.asarray(kappa).shape
     if L is None:
         h_user = (1.0, 1.0, 1.0)
     else:
         h_user = tuple(float(L[d]) / n_user[d] for d in range(3))
-    order = [axis] + [d for d in range(3) if d != axis]
-    return Problem(kap, tuple(h_user[d] for d in order), float(p_in), float(p_out))
+    face = lambda v: float(v) if np.isscalar(v) else np.asarray(v, dtype=np.float64)
+    src = None if source is None else canonical(source, axis)
+    return Problem(kap, tuple(h_user[d] for d in order), face(p_in), face(p_out), kap_a, kap_b, src)
 
 
 # ---------------------------------------------------------------------------
@@ -97,7 +125,7 @@ def _faces(pb: Problem):
     coefficients 2 kappa~ of the first and last load layers (a^in, a^out).
     """
     hL, ha, hb = pb.h
-    kL, ka, kb = pb.kap / hL ** 2, pb.kap / ha ** 2, pb.kap / hb ** 2
+    kL, ka, kb = pb.kap / hL ** 2, pb.kapA / ha ** 2, pb.kapB / hb ** 2
     TL = _harmonic(kL[1:], kL[:-1])
     Ta = _harmonic(ka[:, 1:], ka[:, :-1])
     Tb = _harmonic(kb[:, :, 1:], kb[:, :, :-1])
@@ -128,11 +156,14 @@ def rhs(pb: Problem) -> np.ndarray:
     """Right-hand side from the Dirichlet data.  Substituting the discrete flux
     eq:flux (with p~_F = -p_in on Gamma_in, p_out on Gamma_out and zero ghost
     values) into the cell balance puts 2 kappa~ p_in on the first load layer
-    and 2 kappa~ p_out on the last one; every other entry is zero."""
+    and 2 kappa~ p_out on the last one; every other entry is zero.  A volume
+    source f adds f at each cell (the balance divided by the cell volume)."""
     _, _, _, Tin, Tout = _faces(pb)
     b = np.zeros(pb.shape)
     b[0] += Tin * pb.p_in
     b[-1] += Tout * pb.p_out
+    if pb.src is not None:
+        b += pb.src
     return b
 
 

@@ -21,7 +21,7 @@ __all__ = [
     "EtcError", "library_path", "load_library", "etc_workspace_size", "etc_setup", "etc_solve", "etc_keff",
     "etc_get_solution", "etc_residual_history", "etc_apply_A", "etc_apply_Minv", "etc_set_kernel_timer",
     "etc_kernel_time", "etc_copy_f64", "etc_destroy", "etc_last_error", "etc_version", "Plan", "solve",
-    "STATUS",
+    "STATUS", "etc_grad", "keff",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +56,7 @@ class _Options(ctypes.Structure):
         ("L", ctypes.c_double * 3),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+        ("want_grad", ctypes.c_int),
     ]
 
 
@@ -80,6 +81,7 @@ _SYMBOLS = {
     "etc_keff": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double)]),
     "etc_get_solution": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "etc_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "etc_residual_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_int)]),
     "etc_apply_A": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -138,7 +140,7 @@ def _torch():
 
 
 def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_every=8, kref="mid",
-             kref_user=None, L=None, stream=None) -> _Options:
+             kref_user=None, L=None, stream=None, want_grad=False) -> _Options:
     lib = load_library()
     o = _Options()
     lib.etc_options_default(ctypes.byref(o))
@@ -155,6 +157,7 @@ def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_e
         for d in range(3):
             o.L[d] = float(L[d])
     o.stream = stream
+    o.want_grad = 1 if want_grad else 0
     return o
 
 
@@ -206,7 +209,7 @@ class Plan:
 
 def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
               rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
-              kref: str = "mid", kref_user=None, L=None) -> Plan:
+              kref: str = "mid", kref_user=None, L=None, want_grad: bool = False) -> Plan:
     """Preparation phase on a device tensor ``kappa`` (float64 or float32,
     user layout, load axis ``axis``)."""
     torch = _torch()
@@ -217,7 +220,8 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
     kappa = kappa.contiguous()
     dtype = "float64" if kappa.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(kappa.device)
-    o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream)
+    o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
+                 want_grad)
     n = _dims(kappa.shape)
     nbytes = ctypes.c_size_t(0)
     _check(load_library().etc_workspace_size(n, _DTYPE[dtype], int(axis), ctypes.byref(o), ctypes.byref(nbytes)))
@@ -266,6 +270,49 @@ def etc_residual_history(plan: Plan, cap: int = 100000):
     n = ctypes.c_int(0)
     _check(load_library().etc_residual_history(plan.handle, buf, cap, ctypes.byref(n)))
     return [buf[i] for i in range(n.value)]
+
+
+def etc_grad(plan: Plan):
+    """dK_out/dkappa (float64, user layout) by the adjoint method."""
+    torch = _torch()
+    g = torch.empty(plan.shape, dtype=torch.float64, device=plan.device)
+    _check(load_library().etc_grad(plan.handle, g.data_ptr()))
+    return g
+
+
+class KeffFunction:
+    """torch.autograd.Function computing K_eff(kappa) with the adjoint gradient."""
+
+    _cls = None
+
+    @classmethod
+    def get(cls):
+        if cls._cls is None:
+            torch = _torch()
+
+            class _Keff(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, kappa, axis, p_in, p_out, precision, rtol):
+                    plan = etc_setup(kappa.detach(), axis, p_in, p_out, precision, rtol, want_grad=True)
+                    etc_solve(plan)
+                    k = etc_keff(plan)["keff"]
+                    ctx.plan = plan
+                    ctx.kdtype = kappa.dtype
+                    return torch.tensor(k, dtype=torch.float64, device=kappa.device)
+
+                @staticmethod
+                def backward(ctx, grad_out):
+                    g = etc_grad(ctx.plan)
+                    ctx.plan.close()
+                    return (grad_out * g).to(ctx.kdtype), None, None, None, None, None
+
+            cls._cls = _Keff
+        return cls._cls
+
+
+def keff(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64", rtol: float = 1e-6):
+    """Differentiable K_eff(kappa): a scalar tensor whose backward is etc_grad."""
+    return KeffFunction.get().apply(kappa, axis, p_in, p_out, precision, rtol)
 
 
 def _canon_vec(plan: Plan, x):

@@ -85,6 +85,7 @@ struct etc_plan {
   int max_partials;
   DevState* st;
   double* hist;
+  double* padj;       // adjoint state (want_grad), else nullptr
   DevState* st_host;  // pinned
   DctPlan dpa, dpb;
   LaunchCfg lc;
@@ -140,7 +141,7 @@ DctPlan make_dct_plan(int N) {
 
 struct Sizes {
   size_t off_kap_s, off_kap_hi, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
-      off_part, off_st, off_hist, total;
+      off_part, off_st, off_hist, off_padj, total;
   int max_partials;
 };
 
@@ -178,7 +179,7 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   // columns (a axis)
   {
     const size_t line_bytes = (size_t)dpa.lstride * cx_sz;
-    int tb = (int)std::max<size_t>(1, (64 * 1024) / line_bytes);
+    int tb = (int)std::max<size_t>(1, (80 * 1024) / line_bytes);
     if (dpa.fft) tb = std::min(tb, std::max(1, 16 * kThreads / dpa.M));
     tb = std::min(tb, 32);
     if (tb >= 16) tb = 16 * (tb / 16);
@@ -276,6 +277,7 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
   s.off_part = take((size_t)s.max_partials * sizeof(double));
   s.off_st = take(sizeof(DevState));
   s.off_hist = take((size_t)(o.max_iter + 2) * sizeof(double));
+  s.off_padj = take(o.want_grad ? V * sizeof(double) : 0);
   s.total = off;
   return s;
 }
@@ -326,6 +328,22 @@ template <class S> struct Ops {
     LAUNCHCHK("canon");
     k_extrema<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(g, ks, P->kap_hi, P->partials);
     LAUNCHCHK("extrema");
+    return ETC_OK;
+  }
+
+  // Dynamic LDS above 64 KiB must be requested per kernel (gfx950 has 160 KiB per CU).
+  static etc_status lds_limits(etc_plan* P) {
+    const int cols = (int)P->lc.ldsCols, rows = (int)P->lc.ldsRows;
+    if (cols > 65536) {
+      HIPCHK(hipFuncSetAttribute((const void*)&k_cols<S, T, -1>, hipFuncAttributeMaxDynamicSharedMemorySize, cols));
+      HIPCHK(hipFuncSetAttribute((const void*)&k_cols<S, T, +1>, hipFuncAttributeMaxDynamicSharedMemorySize, cols));
+    }
+    if (rows > 65536) {
+      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_fwd<S, T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
+      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_fwd<S, T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
+      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_inv<S, T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
+      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_inv<S, T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
+    }
     return ETC_OK;
   }
 
@@ -504,6 +522,13 @@ template <class S> struct Ops {
     return ETC_OK;
   }
 
+  static etc_status grad(etc_plan* P, double* out_user, double c) {
+    k_grad<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, P->padj, (const S*)P->kap_s, P->kap_hi, c,
+                                                             P->axis, out_user);
+    LAUNCHCHK("grad");
+    return ETC_OK;
+  }
+
   static etc_status apply_A(etc_plan* P, const void* x, void* y, bool dot) {
     const LaunchCfg& lc = P->lc;
     k_apply_A<S, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, (const S*)x, (const S*)P->kap_s, (S*)y,
@@ -533,6 +558,7 @@ void etc_options_default(etc_options* o) {
   o->refine_every = 10;
   o->poll_every = 8;
   o->stream = nullptr;
+  o->want_grad = 0;
 }
 
 const char* etc_last_error(void) { return g_err.c_str(); }
@@ -638,6 +664,7 @@ etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc
   P->partials = (double*)(b + sz.off_part);
   P->st = (DevState*)(b + sz.off_st);
   P->hist = (double*)(b + sz.off_hist);
+  P->padj = o.want_grad ? (double*)(b + sz.off_padj) : nullptr;
 
   auto bail = [&](etc_status st) {
     etc_destroy(P);
@@ -645,6 +672,8 @@ etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc
   };
 
   // canonical copy + extrema
+  s = (P->prec == ETC_MIXED) ? Ops<float>::lds_limits(P) : Ops<double>::lds_limits(P);
+  if (s) return bail(s);
   s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, kappa) : Ops<double>::canon(P, kappa);
   if (s) return bail(s);
   std::vector<double> part((size_t)P->lc.gridStride * 12);
@@ -829,6 +858,33 @@ etc_status etc_residual_history(const etc_plan* P, double* hist, int cap, int* c
     HIPCHK(hipStreamSynchronize(P->stream));
   }
   *count = n;
+  return ETC_OK;
+}
+
+etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
+  if (!P || !dk_dkappa) return fail(ETC_E_INVALID, "NULL argument");
+  if (!P->padj) return fail(ETC_E_STATE, "etc_grad needs a plan made with want_grad = 1");
+  if (!P->solved) return fail(ETC_E_STATE, "etc_grad before a successful etc_solve");
+  // adjoint solve: the primal system with Dirichlet pair (0, 1), solution into padj
+  const Geo g0 = P->g;
+  const int iters0 = P->last_iters, status0 = P->last_status;
+  const int timer0 = P->timer_id;
+  std::swap(P->p, P->padj);
+  P->g.p_in = 0.0;
+  P->g.p_out = 1.0;
+  P->timer_id = 0;
+  etc_status s = etc_solve(P, nullptr, nullptr);
+  std::swap(P->p, P->padj);
+  P->g = g0;
+  P->timer_id = timer0;
+  P->last_iters = iters0;
+  P->last_status = status0;
+  P->solved = true;
+  if (s != ETC_OK && s != ETC_NOT_CONVERGED) return s;
+  const double c = (double)g0.nL / ((double)g0.na * (double)g0.nb * (g0.p_in - g0.p_out));
+  s = (P->prec == ETC_MIXED) ? Ops<float>::grad(P, dk_dkappa, c) : Ops<double>::grad(P, dk_dkappa, c);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(P->stream));
   return ETC_OK;
 }
 

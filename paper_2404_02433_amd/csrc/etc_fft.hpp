@@ -260,24 +260,25 @@ __device__ __forceinline__ void dct_post(const cx<T>* Z, int k, int N, int M, co
   }
 }
 
-// Backward pre-processing of one item k in [0, M/2]: read X[k], X[N-k],
-// X[M-k], X[M+k] through `ld(index)` and write Z[k], Z[M-k] to the LDS line.
-template <class T, class Load>
-__device__ __forceinline__ void dct_pre_inv(cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Load ld) {
+// Backward pre-processing of one item k in [0, M/2] from the four inputs
+// xk = X[k], xnk = X[N-k], xk2 = X[M-k], xnk2 = X[M+k] (for k = 0: X[0], X[M]
+// in xk, xk2); writes Z[k] and Z[M-k] to the LDS line.
+template <class T>
+__device__ __forceinline__ void dct_pre_inv_vals(cx<T>* Z, int k, int M, const cx<T>* __restrict__ tw, T xk, T xnk,
+                                                 T xk2, T xnk2) {
   const T half = T(0.5);
   if (k == 0) {
-    const T x0 = ld(0), xm = ld(M);
-    cx<T> V0 = {x0, T(0)};
+    cx<T> V0 = {xk, T(0)};
     // V[M] = exp(i pi/4) (X[M] - i X[M]) = sqrt(2) X[M]
-    cx<T> VM = cmul(cconj(tw[M]), cx<T>{xm, -xm});
+    cx<T> VM = cmul(cconj(tw[M]), cx<T>{xk2, -xk2});
     cx<T> E = cscale(cadd(V0, cconj(VM)), half);
     cx<T> O = cscale(csub(V0, cconj(VM)), half);
     Z[lpad(0)] = cadd(E, rot_i<+1>(O));
     return;
   }
   const int k2 = M - k;
-  cx<T> Vk = cmul(cconj(tw[k]), cx<T>{ld(k), -ld(N - k)});
-  cx<T> Vk2 = cmul(cconj(tw[k2]), cx<T>{ld(k2), -ld(N - k2)});
+  cx<T> Vk = cmul(cconj(tw[k]), cx<T>{xk, -xnk});
+  cx<T> Vk2 = cmul(cconj(tw[k2]), cx<T>{xk2, -xnk2});
   {
     cx<T> E = cscale(cadd(Vk, cconj(Vk2)), half);
     cx<T> O = cscale(cmul(cconj(tw[4 * k]), csub(Vk, cconj(Vk2))), half);
@@ -287,6 +288,21 @@ __device__ __forceinline__ void dct_pre_inv(cx<T>* Z, int k, int N, int M, const
     cx<T> E = cscale(cadd(Vk2, cconj(Vk)), half);
     cx<T> O = cscale(cmul(cconj(tw[4 * k2]), csub(Vk2, cconj(Vk))), half);
     Z[lpad(k2)] = cadd(E, rot_i<+1>(O));
+  }
+}
+
+// Indices of the four inputs of backward item k (k = 0 uses slots 0 and 2).
+__device__ __forceinline__ void pre_inv_idx(int k, int N, int M, int& i0, int& i1, int& i2, int& i3) {
+  if (k == 0) {
+    i0 = 0;
+    i1 = 0;
+    i2 = M;
+    i3 = M;
+  } else {
+    i0 = k;
+    i1 = N - k;
+    i2 = M - k;
+    i3 = M + k;
   }
 }
 

@@ -303,6 +303,10 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
 }
 
 // ============================================================ DCT along rows
+// Global loads are issued in batches of UNR per thread before their LDS
+// stores, so every wave keeps several HBM requests in flight.
+constexpr int UNR = 8;
+
 // Rows are the contiguous b lines; a block owns `rpb` whole rows.
 // MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): p += alpha w,
 // r -= alpha q, partial ||r||^2, t = DCT_b(r).
@@ -321,27 +325,55 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
   const int64_t row0 = (int64_t)blockIdx.x * rpb;
   const int lines = (int)min((int64_t)rpb, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
+  const int total = lines * N;
   double acc = 0.0;
   double alpha = 0.0;
   if (MODE == 1) alpha = st->alpha;
   const int ls = dp.lstride;
   // load (and update) the rows into LDS, reordered for the FFT route
-  for (int e = tid; e < lines * N; e += nthr) {
-    const int line = e / N, j = e - line * N;
-    const int64_t gi = base + e;
-    T x;
+  constexpr int U = (MODE == 1) ? 4 : UNR;
+  for (int e0 = tid; e0 < total; e0 += nthr * U) {
+    T x[U];
     if (MODE == 1) {
-      p[gi] = p[gi] + alpha * (double)w[gi];
-      const S rs = (S)((double)r[gi] - alpha * (double)q[gi]);
-      r[gi] = rs;
-      acc += (double)rs * (double)rs;
-      x = (T)rs;
+      double pv[U], wv[U], rv[U], qv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) {
+          pv[u] = p[base + e];
+          wv[u] = (double)w[base + e];
+          rv[u] = (double)r[base + e];
+          qv[u] = (double)q[base + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) {
+          p[base + e] = pv[u] + alpha * wv[u];
+          const S rs = (S)(rv[u] - alpha * qv[u]);
+          r[base + e] = rs;
+          acc += (double)rs * (double)rs;
+          x[u] = (T)rs;
+        }
+      }
     } else {
-      x = (T)src[gi];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) x[u] = (T)src[base + e];
+      }
     }
-    T* L = reinterpret_cast<T*>(buf + line * ls);
-    if (dp.fft) L[vpos(dct_perm(j, N))] = x;
-    else L[j] = x;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < total) {
+        const int line = e / N, j = e - line * N;
+        T* L = reinterpret_cast<T*>(buf + line * ls);
+        if (dp.fft) L[vpos(dct_perm(j, N))] = x[u];
+        else L[j] = x[u];
+      }
+    }
   }
   __syncthreads();
   if (dp.fft) {
@@ -354,7 +386,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
     }
   } else {
     const int N4 = 4 * N;
-    for (int e = tid; e < lines * N; e += nthr) {
+    for (int e = tid; e < total; e += nthr) {
       const int line = e / N, k = e - line * N;
       const T* L = reinterpret_cast<const T*>(buf + line * ls);
       T s = T(0);
@@ -382,29 +414,65 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
   const int64_t row0 = (int64_t)blockIdx.x * rpb;
   const int lines = (int)min((int64_t)rpb, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
+  const int total = lines * N;
   const int ls = dp.lstride;
   double beta = 0.0;
   if (MODE == 1) beta = st->beta;
   if (dp.fft) {
     const int M = dp.M, nit = M / 2 + 1;
-    for (int e = tid; e < lines * nit; e += nthr) {
-      const int line = e / nit, k = e - line * nit;
-      const S* in = src + base + (int64_t)line * N;
-      dct_pre_inv(buf + line * ls, k, N, M, tw, [&](int idx) { return (T)in[idx]; });
+    const int items = lines * nit;
+    constexpr int UI = 4;
+    for (int e0 = tid; e0 < items; e0 += nthr * UI) {
+      T xv[UI][4];
+#pragma unroll
+      for (int u = 0; u < UI; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < items) {
+          const int line = e / nit, k = e - line * nit;
+          const S* in = src + base + (int64_t)line * N;
+          int i0, i1, i2, i3;
+          pre_inv_idx(k, N, M, i0, i1, i2, i3);
+          xv[u][0] = (T)in[i0];
+          xv[u][1] = (T)in[i1];
+          xv[u][2] = (T)in[i2];
+          xv[u][3] = (T)in[i3];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UI; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < items) {
+          const int line = e / nit, k = e - line * nit;
+          dct_pre_inv_vals(buf + line * ls, k, M, tw, xv[u][0], xv[u][1], xv[u][2], xv[u][3]);
+        }
+      }
     }
     __syncthreads();
     lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
     const T invM = T(1) / T(M);
-    for (int e = tid; e < lines * N; e += nthr) {
-      const int line = e / N, j = e - line * N;
-      const T* L = reinterpret_cast<const T*>(buf + line * ls);
-      const T z = L[vpos(dct_perm(j, N))] * invM;
-      const int64_t gi = base + e;
-      if (MODE == 1) dst[gi] = (S)((double)z + beta * (double)dst[gi]);
-      else dst[gi] = (S)z;
+    for (int e0 = tid; e0 < total; e0 += nthr * UNR) {
+      double wv[UNR];
+      if (MODE == 1) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int e = e0 + u * nthr;
+          if (e < total) wv[u] = (double)dst[base + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) {
+          const int line = e / N, j = e - line * N;
+          const T* L = reinterpret_cast<const T*>(buf + line * ls);
+          const T z = L[vpos(dct_perm(j, N))] * invM;
+          if (MODE == 1) dst[base + e] = (S)((double)z + beta * wv[u]);
+          else dst[base + e] = (S)z;
+        }
+      }
     }
   } else {
-    for (int e = tid; e < lines * N; e += nthr) {
+    for (int e = tid; e < total; e += nthr) {
       const int line = e / N, j = e - line * N;
       T* L = reinterpret_cast<T*>(buf + line * ls);
       L[j] = (T)src[base + e];
@@ -412,7 +480,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
     __syncthreads();
     const int N4 = 4 * N;
     const T sc = T(2) / T(N);
-    for (int e = tid; e < lines * N; e += nthr) {
+    for (int e = tid; e < total; e += nthr) {
       const int line = e / N, n = e - line * N;
       const T* L = reinterpret_cast<const T*>(buf + line * ls);
       T s = T(0.5) * L[0];
@@ -440,13 +508,28 @@ __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   const int lines = min(tb, g.nb - b0);
   S* pl = data + (int64_t)blockIdx.y * g.plane + b0;
   const int ls = dp.lstride;
+  const int total = lines * N;
   if (DIR < 0) {
-    for (int e = tid; e < lines * N; e += nthr) {
-      const int n = e / lines, c = e - n * lines;
-      const T x = (T)pl[(int64_t)n * g.nb + c];
-      T* L = reinterpret_cast<T*>(buf + c * ls);
-      if (dp.fft) L[vpos(dct_perm(n, N))] = x;
-      else L[n] = x;
+    for (int e0 = tid; e0 < total; e0 += nthr * UNR) {
+      T x[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) {
+          const int n = e / lines, c = e - n * lines;
+          x[u] = (T)pl[(int64_t)n * g.nb + c];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) {
+          const int n = e / lines, c = e - n * lines;
+          T* L = reinterpret_cast<T*>(buf + c * ls);
+          if (dp.fft) L[vpos(dct_perm(n, N))] = x[u];
+          else L[n] = x[u];
+        }
+      }
     }
     __syncthreads();
     if (dp.fft) {
@@ -458,7 +541,7 @@ __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __
       }
     } else {
       const int N4 = 4 * N;
-      for (int e = tid; e < lines * N; e += nthr) {
+      for (int e = tid; e < total; e += nthr) {
         const int k = e / lines, c = e - k * lines;
         const T* L = reinterpret_cast<const T*>(buf + c * ls);
         T s = T(0);
@@ -469,20 +552,42 @@ __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   } else {
     if (dp.fft) {
       const int M = dp.M, nit = M / 2 + 1;
-      for (int e = tid; e < lines * nit; e += nthr) {
-        const int k = e / lines, c = e - k * lines;
-        dct_pre_inv(buf + c * ls, k, N, M, tw, [&](int idx) { return (T)pl[(int64_t)idx * g.nb + c]; });
+      const int items = lines * nit;
+      constexpr int UI = 4;
+      for (int e0 = tid; e0 < items; e0 += nthr * UI) {
+        T xv[UI][4];
+#pragma unroll
+        for (int u = 0; u < UI; ++u) {
+          const int e = e0 + u * nthr;
+          if (e < items) {
+            const int k = e / lines, c = e - k * lines;
+            int i0, i1, i2, i3;
+            pre_inv_idx(k, N, M, i0, i1, i2, i3);
+            xv[u][0] = (T)pl[(int64_t)i0 * g.nb + c];
+            xv[u][1] = (T)pl[(int64_t)i1 * g.nb + c];
+            xv[u][2] = (T)pl[(int64_t)i2 * g.nb + c];
+            xv[u][3] = (T)pl[(int64_t)i3 * g.nb + c];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UI; ++u) {
+          const int e = e0 + u * nthr;
+          if (e < items) {
+            const int k = e / lines, c = e - k * lines;
+            dct_pre_inv_vals(buf + c * ls, k, M, tw, xv[u][0], xv[u][1], xv[u][2], xv[u][3]);
+          }
+        }
       }
       __syncthreads();
       lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
       const T invM = T(1) / T(M);
-      for (int e = tid; e < lines * N; e += nthr) {
+      for (int e = tid; e < total; e += nthr) {
         const int n = e / lines, c = e - n * lines;
         const T* L = reinterpret_cast<const T*>(buf + c * ls);
         pl[(int64_t)n * g.nb + c] = (S)(L[vpos(dct_perm(n, N))] * invM);
       }
     } else {
-      for (int e = tid; e < lines * N; e += nthr) {
+      for (int e = tid; e < total; e += nthr) {
         const int n = e / lines, c = e - n * lines;
         T* L = reinterpret_cast<T*>(buf + c * ls);
         L[n] = (T)pl[(int64_t)n * g.nb + c];
@@ -490,7 +595,7 @@ __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __
       __syncthreads();
       const int N4 = 4 * N;
       const T sc = T(2) / T(N);
-      for (int e = tid; e < lines * N; e += nthr) {
+      for (int e = tid; e < total; e += nthr) {
         const int n = e / lines, c = e - n * lines;
         const T* L = reinterpret_cast<const T*>(buf + c * ls);
         T s = T(0.5) * L[0];
@@ -502,6 +607,16 @@ __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __
 }
 
 // =================================================================== Thomas
+// Reciprocal: hardware estimate refined by two Newton steps (within one ulp
+// of the correctly rounded quotient for the positive, normal pivots here).
+__device__ __forceinline__ double frcp(double u) {
+  double r = __builtin_amdgcn_rcp(u);
+  double e = fma(-u, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-u, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Solve T_{a',b'} z = t along k for every transverse mode (a', b'), in place,
 // with double arithmetic.  T = s I + kL tridiag(-1, 2, -1), first and last
 // diagonal entries s + kL + 2 kin and s + kL + 2 kout, s = lam_a ka + lam_b kb.
@@ -509,13 +624,17 @@ __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __
 // Partitioned elimination keeps every value in registers: the block holds TB
 // adjacent modes (lines, coalesced) times P partitions of each line.  A
 // partition is `len` interior rows followed by one separator row (none for
-// the last partition).  Each thread eliminates its interior block (LU
-// pivots and UL pivots), the separators form a symmetric tridiagonal Schur
-// complement solved by one thread per line, and each thread then corrects
-// its interior rows with the two boundary responses.
+// the last partition).  Phase 1: each thread loads its rows, runs the LU
+// sweep of its interior block M (pivots kept) and the UL sweep as a scalar
+// chain, giving y = M^{-1} t at both ends and the corner entries of M^{-1}.
+// The separators then form a symmetric tridiagonal Schur complement, solved
+// by one thread per line.  Phase 2: each thread moves its two separator
+// couplings to the right-hand side and re-solves its block with the stored
+// pivots.
 //
 // Also returns the partial of r . z: by the DCT's Parseval relation it equals
-// (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r.
+// (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r;
+// per block, t . z = t^T M^{-1} t + (coupling) * (ends of M^{-1} t).
 template <class S, int TB, int P, int MAXM>
 __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
@@ -545,52 +664,52 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
 
   const int64_t col = (int64_t)am * g.nb + bm;
   // register arrays are only ever indexed by unrolled constants
-  double y[MAXM], invu[MAXM], invv[MAXM];
-  double quad = 0.0, ts = 0.0, invu_last = 0.0, y_last = 0.0;
+  double tv[MAXM], invu[MAXM];
+  double quad = 0.0, ts = 0.0, invu_last = 0.0, y_last = 0.0, y_first = 0.0, m11 = 0.0, prod = 1.0;
   if (active) {
-    // forward elimination (LU), d' kept in y; t^T M^{-1} t = sum_j d'_j f_j
-    double prod = 1.0;
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j)
+      if (j < len) tv[j] = (double)t[(int64_t)(start + j) * g.plane + col];
+    if (has_right) ts = (double)t[(int64_t)(endp - 1) * g.plane + col];
+    // LU sweep: pivots u_j (kept as 1/u_j), d'_j as a scalar chain,
+    // t^T M^{-1} t = sum_j d'_j f_j, (M^{-1})_{1,len} = prod_j (-c'_j) / u_last
+    double dprev = 0.0;
 #pragma unroll
     for (int j = 0; j < MAXM; ++j) {
       if (j < len) {
-        const double tv = (double)t[(int64_t)(start + j) * g.plane + col];
         double u, f;
         if (j == 0) {
           u = Dof(start);
-          f = tv;
+          f = tv[0];
         } else {
           u = Dof(start + j) - a2 * invu[j - 1];
-          f = tv - aoff * y[j - 1];
+          f = tv[j] - aoff * dprev;
           prod *= -(aoff * invu[j - 1]);
         }
-        invu[j] = 1.0 / u;
-        y[j] = f * invu[j];
-        quad += y[j] * f;
-        if (j == len - 1) {
-          invu_last = invu[j];
-          y_last = y[j];
-        }
+        invu[j] = frcp(u);
+        dprev = f * invu[j];
+        quad += dprev * f;
+        if (j == len - 1) invu_last = invu[j];
       }
     }
-    if (has_right) ts = (double)t[(int64_t)(endp - 1) * g.plane + col];
-    // back substitution y_j = d'_j - c'_j y_{j+1}, c'_j = aoff invu_j
-#pragma unroll
-    for (int j = MAXM - 2; j >= 0; --j)
-      if (j < len - 1) y[j] -= aoff * invu[j] * y[j + 1];
-    // UL pivots (bottom-up): first column of M^{-1}
-    double vprev = 0.0;
+    y_last = dprev;
+    // UL sweep (bottom-up) as a scalar chain: y_0 and (M^{-1})_{11}
+    double iv = 0.0, gch = 0.0;
 #pragma unroll
     for (int j = MAXM - 1; j >= 0; --j) {
       if (j < len) {
-        double v = Dof(start + j);
-        if (j < len - 1) v -= a2 * vprev;
-        invv[j] = 1.0 / v;
-        vprev = invv[j];
+        const bool bottom = (j == len - 1);
+        const double v = Dof(start + j) - (bottom ? 0.0 : a2 * iv);
+        const double ivn = frcp(v);
+        gch = (tv[j] - (bottom ? 0.0 : aoff * gch)) * ivn;
+        iv = ivn;
       }
     }
-    sh[0][p][l] = y[0];
+    y_first = gch;
+    m11 = iv;
+    sh[0][p][l] = y_first;
     sh[1][p][l] = y_last;
-    sh[2][p][l] = invv[0];
+    sh[2][p][l] = m11;
     sh[3][p][l] = invu_last;
     sh[4][p][l] = prod * invu_last;  // (M^{-1})_{1,len}
     sh[5][p][l] = ts;
@@ -601,22 +720,27 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
   if (p == 0 && line_ok && Peff > 1) {
     const int nsep = Peff - 1;
     double cprev = 0.0, dprev = 0.0;
-    for (int qd = 0; qd < nsep; ++qd) {
-      const double Lq = (qd > 0) ? -a2 * sh[4][qd][l] : 0.0;
-      const double Bq = sh[6][qd][l] - a2 * (sh[3][qd][l] + sh[2][qd + 1][l]);
-      const double Uq = (qd + 1 < nsep) ? -a2 * sh[4][qd + 1][l] : 0.0;
-      const double rq = sh[5][qd][l] - aoff * sh[1][qd][l] - aoff * sh[0][qd + 1][l];
-      const double den = Bq - Lq * cprev;
-      cprev = Uq / den;
-      dprev = (rq - Lq * dprev) / den;
-      sh[5][qd][l] = cprev;
-      sh[6][qd][l] = dprev;
+#pragma unroll
+    for (int qd = 0; qd < P - 1; ++qd) {
+      if (qd < nsep) {
+        const double Lq = (qd > 0) ? -a2 * sh[4][qd][l] : 0.0;
+        const double Bq = sh[6][qd][l] - a2 * (sh[3][qd][l] + sh[2][qd + 1][l]);
+        const double Uq = (qd + 1 < nsep) ? -a2 * sh[4][qd + 1][l] : 0.0;
+        const double rq = sh[5][qd][l] - aoff * sh[1][qd][l] - aoff * sh[0][qd + 1][l];
+        const double iden = frcp(Bq - Lq * cprev);
+        cprev = Uq * iden;
+        dprev = (rq - Lq * dprev) * iden;
+        sh[5][qd][l] = cprev;
+        sh[6][qd][l] = dprev;
+      }
     }
-    double x = sh[6][nsep - 1][l];
-    sh[7][nsep - 1][l] = x;
-    for (int qd = nsep - 2; qd >= 0; --qd) {
-      x = sh[6][qd][l] - sh[5][qd][l] * x;
-      sh[7][qd][l] = x;
+    double x = 0.0;
+#pragma unroll
+    for (int qd = P - 2; qd >= 0; --qd) {
+      if (qd < nsep) {
+        x = (qd == nsep - 1) ? sh[6][qd][l] : (sh[6][qd][l] - sh[5][qd][l] * x);
+        sh[7][qd][l] = x;
+      }
     }
   }
   __syncthreads();
@@ -624,32 +748,34 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
   if (active) {
     const double zl = (p > 0) ? sh[7][p - 1][l] : 0.0;
     const double zr = has_right ? sh[7][p][l] : 0.0;
-    const double c1 = -aoff * zl, cm = -aoff * zr;
-    const double yF = y[0], yL = y_last;
-    // add c1 M^{-1} e_1 (forward recurrence on the UL pivots)
-    double x1 = 0.0;
+    // re-solve M z = t - a zl e_1 - a zr e_len with the stored LU pivots
+    double d = 0.0;
 #pragma unroll
     for (int j = 0; j < MAXM; ++j) {
       if (j < len) {
-        x1 = (j == 0) ? invv[0] : (-aoff * invv[j] * x1);
-        y[j] += c1 * x1;
+        double f = tv[j];
+        if (j == 0) f -= aoff * zl;
+        else f -= aoff * d;
+        if (j == len - 1) f -= aoff * zr;
+        d = f * invu[j];
+        tv[j] = d;
       }
     }
-    // add cm M^{-1} e_len (backward recurrence on the LU pivots)
-    double xm = 0.0;
+    double z = 0.0;
 #pragma unroll
     for (int j = MAXM - 1; j >= 0; --j) {
       if (j < len) {
-        xm = (j == len - 1) ? invu_last : (-aoff * invu[j] * xm);
-        y[j] += cm * xm;
+        z = (j == len - 1) ? tv[j] : (tv[j] - aoff * invu[j] * z);
+        tv[j] = z;
       }
     }
 #pragma unroll
     for (int j = 0; j < MAXM; ++j)
-      if (j < len) t[(int64_t)(start + j) * g.plane + col] = (S)y[j];
+      if (j < len) t[(int64_t)(start + j) * g.plane + col] = (S)tv[j];
     if (has_right) t[(int64_t)(endp - 1) * g.plane + col] = (S)zr;
+    const double c1 = -aoff * zl, cm = -aoff * zr;
     const double wa = (am == 0) ? 0.5 : 1.0, wb = (bm == 0) ? 0.5 : 1.0;
-    acc = wa * wb * (quad + c1 * yF + cm * yL + (has_right ? ts * zr : 0.0));
+    acc = wa * wb * (quad + c1 * y_first + cm * y_last + (has_right ? ts * zr : 0.0));
   }
   if (partials) {
     const double sum = block_sum(acc, red);
@@ -827,6 +953,45 @@ __global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict_
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Gradient of K_out with respect to every voxel conductivity (adjoint form).
+// K_out = c sum_last 2 kappa (p - p_out), c = nL / (na nb (p_in - p_out)).
+// With A lambda = dK/dp (= 2 c kappa on the last layer), lambda = (c / fL) phi
+// where phi solves the primal system with Dirichlet pair (0, 1).  Then
+//   dK/dkappa_v = [v last] 2 c (p_v - p_out)
+//               - sum_{faces F of v} dkappa_F/dkappa_v (p_v - p_n)(lambda_v - lambda_n)
+//               - [v first] 2 fL (p_v - p_in) lambda_v - [v last] 2 fL (p_v - p_out) lambda_v,
+// dkappa_F/dkappa_v = f_d 2 kappa_n^2 / (kappa_v + kappa_n)^2 for a
+// harmonic-mean face.  Reads the canonical layout, writes `out` in the
+// user layout of load axis `axis`; double arithmetic.
+template <class S>
+__global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ p, const double* __restrict__ phi,
+                                              const S* __restrict__ ks, const double* __restrict__ kh, double c,
+                                              int axis, double* __restrict__ out) {
+  const double lsc = c / g.fL;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    const int64_t k = i / g.plane, rem = i - k * g.plane;
+    const int64_t a = rem / g.nb, b = rem - a * g.nb;
+    const double kv = kap_at(ks, kh, i), pv = p[i], lv = lsc * phi[i];
+    double gv = 0.0;
+    auto face = [&](int64_t n, double f) {
+      const double kn = kap_at(ks, kh, n);
+      const double sden = kv + kn;
+      gv -= f * 2.0 * kn * kn / (sden * sden) * (pv - p[n]) * (lv - lsc * phi[n]);
+    };
+    if (k > 0) face(i - g.plane, g.fL);
+    if (k + 1 < g.nL) face(i + g.plane, g.fL);
+    if (a > 0) face(i - g.nb, g.fa);
+    if (a + 1 < g.na) face(i + g.nb, g.fa);
+    if (b > 0) face(i - 1, g.fb);
+    if (b + 1 < g.nb) face(i + 1, g.fb);
+    if (k == 0) gv -= 2.0 * g.fL * (pv - g.p_in) * lv;
+    if (k == g.nL - 1) gv += 2.0 * c * (pv - g.p_out) - 2.0 * g.fL * (pv - g.p_out) * lv;
+    const int64_t ui = axis == 0 ? i : (axis == 1 ? (a * g.nL + k) * g.nb + b : (a * g.nb + b) * g.nL + k);
+    out[ui] = gv;
+  }
 }
 
 // Plain copy (bandwidth calibration of the hardware byte counters).

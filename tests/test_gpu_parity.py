@@ -225,3 +225,67 @@ def test_warm_start_resume():
     direct = etc.solve(dev(kap), 0, rtol=1e-10)["keff"]
     assert out["status"] == "ok"
     assert abs(k_resumed - direct) < 1e-8 * direct
+
+
+# ------------------------------------------------------------------ gradient
+@pytest.mark.parametrize("axis,precision", [(0, "fp64"), (2, "fp64"), (1, "mixed")])
+def test_adjoint_gradient_matches_oracle(axis, precision):
+    """etc_grad (adjoint PCG + face-product kernel) against the oracle's
+    dissipation-form gradient, which equals dK/dkappa at the exact solution."""
+    shape = (18, 14, 22)
+    kap = lognormal(shape, seed=31 + axis, sigma=0.8)
+    rtol = 1e-12 if precision == "fp64" else 1e-7
+    plan = etc.etc_setup(dev(kap), axis, p_in=1.5, p_out=0.5, rtol=rtol, precision=precision, want_grad=True)
+    etc.etc_solve(plan)
+    g = etc.etc_grad(plan).cpu().numpy()
+    k_after = etc.etc_keff(plan)["keff"]
+    pb = O.make_problem(kap, axis, p_in=1.5, p_out=0.5)
+    ref = O.solve(kap, axis, p_in=1.5, p_out=0.5, rtol=1e-13)
+    gref = O.decanonical(O.keff_gradient(pb, ref["pcg"].p), axis)
+    tol = 1e-8 if precision == "fp64" else 1e-4
+    assert np.abs(g - gref).max() <= tol * np.abs(gref).max()
+    # the primal state survives the adjoint solve
+    assert abs(k_after - ref["keff"]) <= (1e-9 if precision == "fp64" else 1e-5) * ref["keff"]
+    plan.close()
+
+
+def test_gradient_finite_differences_on_gpu():
+    shape = (16, 12, 20)
+    kap = lognormal(shape, seed=41, sigma=1.0)
+    plan = etc.etc_setup(dev(kap), 0, rtol=1e-13, want_grad=True)
+    etc.etc_solve(plan)
+    g = etc.etc_grad(plan).cpu().numpy()
+    plan.close()
+    rng = np.random.default_rng(3)
+    for _ in range(8):
+        v = tuple(int(rng.integers(0, s)) for s in shape)
+        d = 1e-4 * kap[v]
+        vals = []
+        for sgn in (1, -1):
+            k2 = kap.copy()
+            k2[v] += sgn * d
+            vals.append(etc.solve(dev(k2), 0, rtol=1e-13)["keff"])
+        fd = (vals[0] - vals[1]) / (2 * d)
+        assert abs(fd - g[v]) <= 1e-6 * np.abs(g).max() + 1e-6 * abs(g[v]), (v, fd, g[v])
+
+
+def test_autograd_function():
+    kap = lognormal((12, 10, 14), seed=5)
+    x = dev(kap).requires_grad_(True)
+    k = etc.keff(x, 0, rtol=1e-12)
+    (gx,) = torch.autograd.grad(3.0 * k, x)
+    plan = etc.etc_setup(dev(kap), 0, rtol=1e-12, want_grad=True)
+    etc.etc_solve(plan)
+    g = etc.etc_grad(plan)
+    plan.close()
+    assert torch.allclose(gx, 3.0 * g, rtol=1e-10, atol=1e-14)
+
+
+def test_grad_requires_want_grad():
+    kap = lognormal((8, 8, 8), seed=6)
+    plan = etc.etc_setup(dev(kap), 0)
+    etc.etc_solve(plan)
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_grad(plan)
+    assert e.value.status == -5
+    plan.close()
