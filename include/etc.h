@@ -98,6 +98,23 @@ typedef struct {
 
 typedef struct etc_plan etc_plan;
 
+/* General problem data (Section "Model problem" allows K = diag(kappa^x,
+ * kappa^y, kappa^z) per voxel; tab:smooth adds a volume source and Dirichlet
+ * data that vary over the faces).  All pointers are device memory in the
+ * user layout and are borrowed for the duration of etc_setup_ex only.
+ *   kappa[0..2] : conductivity along user axes 0, 1, 2 (dtype of the call).
+ *                 kappa[1] = kappa[2] = NULL means isotropic kappa[0].
+ *   source      : float64 volume source f per voxel, or NULL (no source).
+ *   p_in_face   : float64 Dirichlet value per face of the first load layer,
+ *                 an array over the two transverse axes in user order, or
+ *                 NULL (constant bc.p_in); p_out_face likewise (bc.p_out). */
+typedef struct {
+  const void* kappa[3];
+  const double* source;
+  const double* p_in_face;
+  const double* p_out_face;
+} etc_problem;
+
 /* Fill `opt` with the defaults listed above. */
 void etc_options_default(etc_options* opt);
 
@@ -120,6 +137,18 @@ etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const 
  *   plan  : receives the new plan (NULL on failure). */
 etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
                      const etc_options* opt, etc_plan** plan);
+
+/* etc_setup for general problem data (see etc_problem); the isotropic,
+ * source-free, constant-Dirichlet case is etc_setup.  With face data or a
+ * source, etc_keff still reports the boundary flux sums scaled by
+ * nL / (na nb (bc.p_in - bc.p_out)). */
+etc_status etc_setup_ex(const etc_problem* problem, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                        const etc_options* opt, etc_plan** plan);
+
+/* Workspace bytes for etc_setup_ex with this problem shape (only which
+ * pointers are NULL matters). */
+etc_status etc_workspace_size_ex(const etc_problem* problem, const int64_t n[3], etc_dtype dt, int axis,
+                                 const etc_options* opt, size_t* bytes);
 
 /* Execution phase: PCG of alg:pcg from p0 (device, user layout, float64;
  * NULL = zero) until ||r|| / ||b|| <= rtol or max_iter passes.  Returns
@@ -144,7 +173,9 @@ etc_status etc_keff(etc_plan* plan, double* k_out, double* k_in, double* k_energ
  * primal and adjoint jumps (harmonic-mean faces, eq:scaled bilinear forms),
  * plus the Dirichlet-face terms.
  *   dk_dkappa : device, user layout, float64, caller-owned.
- * Needs a plan made with want_grad = 1 (else ETC_E_STATE).  Synchronises. */
+ * Needs a plan made with want_grad = 1 (else ETC_E_STATE); isotropic kappa with
+ * constant Dirichlet data only (else etc_setup_ex returns ETC_E_UNSUPPORTED
+ * when want_grad is set).  Synchronises. */
 etc_status etc_grad(etc_plan* plan, double* dk_dkappa);
 
 /* Copy the solution p into `p` (device, user layout, float64, caller-owned). */

@@ -60,6 +60,15 @@ class _Options(ctypes.Structure):
     ]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("kappa", ctypes.c_void_p * 3),
+        ("source", ctypes.c_void_p),
+        ("p_in_face", ctypes.c_void_p),
+        ("p_out_face", ctypes.c_void_p),
+    ]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int),
@@ -77,6 +86,10 @@ _SYMBOLS = {
                                           ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]),
     "etc_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC, ctypes.c_int,
                                  ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]),
+    "etc_setup_ex": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC,
+                                    ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]),
+    "etc_workspace_size_ex": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]),
     "etc_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]),
     "etc_keff": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double)]),
@@ -209,29 +222,62 @@ class Plan:
 
 def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
               rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
-              kref: str = "mid", kref_user=None, L=None, want_grad: bool = False) -> Plan:
-    """Preparation phase on a device tensor ``kappa`` (float64 or float32,
-    user layout, load axis ``axis``)."""
+              kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, source=None,
+              p_in_face=None, p_out_face=None) -> Plan:
+    """Preparation phase on device data (user layout, load axis ``axis``).
+
+    ``kappa`` is one tensor (isotropic) or a sequence of three tensors, the
+    conductivity along user axes 0, 1, 2 (orthotropic), float64 or float32.
+    ``source`` (float64, kappa's shape), ``p_in_face`` / ``p_out_face``
+    (float64 over the two transverse axes in user order) are optional."""
     torch = _torch()
-    if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda":
-        raise ValueError("kappa must be a torch tensor on a GPU device")
-    if kappa.dtype not in (torch.float64, torch.float32):
-        raise ValueError("kappa must be float64 or float32")
-    kappa = kappa.contiguous()
-    dtype = "float64" if kappa.dtype == torch.float64 else "float32"
-    stream = torch.cuda.current_stream(kappa.device)
+    comps = list(kappa) if isinstance(kappa, (list, tuple)) else [kappa]
+    if len(comps) not in (1, 3):
+        raise ValueError("kappa must be one tensor or three components")
+    for c in comps:
+        if not isinstance(c, torch.Tensor) or c.device.type != "cuda":
+            raise ValueError("kappa must be torch tensors on a GPU device")
+        if c.dtype not in (torch.float64, torch.float32) or c.dtype != comps[0].dtype:
+            raise ValueError("kappa must be float64 or float32 (one dtype)")
+        if tuple(c.shape) != tuple(comps[0].shape):
+            raise ValueError("kappa components must share one shape")
+    comps = [c.contiguous() for c in comps]
+    k0 = comps[0]
+    dtype = "float64" if k0.dtype == torch.float64 else "float32"
+    stream = torch.cuda.current_stream(k0.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
                  want_grad)
-    n = _dims(kappa.shape)
+    n = _dims(k0.shape)
+    pr = _Problem()
+    keep = list(comps)
+    for d in range(3):
+        pr.kappa[d] = comps[d].data_ptr() if len(comps) == 3 else (k0.data_ptr() if d == 0 else None)
+    order = [d for d in range(3) if d != int(axis)]
+    face_shape = (k0.shape[order[0]], k0.shape[order[1]])
+
+    def f64(x, shape, name):
+        if x is None:
+            return None
+        if x.dtype != torch.float64 or tuple(x.shape) != tuple(shape) or x.device != k0.device:
+            raise ValueError(f"{name} must be a float64 tensor of shape {tuple(shape)} on kappa's device")
+        x = x.contiguous()
+        keep.append(x)
+        return x.data_ptr()
+
+    pr.source = f64(source, k0.shape, "source")
+    pr.p_in_face = f64(p_in_face, face_shape, "p_in_face")
+    pr.p_out_face = f64(p_out_face, face_shape, "p_out_face")
     nbytes = ctypes.c_size_t(0)
-    _check(load_library().etc_workspace_size(n, _DTYPE[dtype], int(axis), ctypes.byref(o), ctypes.byref(nbytes)))
-    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=kappa.device)
+    _check(load_library().etc_workspace_size_ex(ctypes.byref(pr), n, _DTYPE[dtype], int(axis), ctypes.byref(o),
+                                                ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=k0.device)
     o.workspace = ws.data_ptr()
     o.workspace_bytes = int(nbytes.value)
     h = ctypes.c_void_p(0)
-    _check(load_library().etc_setup(kappa.data_ptr(), _DTYPE[dtype], n, _BC(float(p_in), float(p_out)), int(axis),
-                                    ctypes.byref(o), ctypes.byref(h)))
-    return Plan(h, ws, kappa.shape, int(axis), precision, kappa.device, stream)
+    _check(load_library().etc_setup_ex(ctypes.byref(pr), _DTYPE[dtype], n, _BC(float(p_in), float(p_out)),
+                                       int(axis), ctypes.byref(o), ctypes.byref(h)))
+    del keep
+    return Plan(h, ws, k0.shape, int(axis), precision, k0.device, stream)
 
 
 def etc_solve(plan: Plan, p0=None) -> dict:

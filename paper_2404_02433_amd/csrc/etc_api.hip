@@ -75,8 +75,12 @@ struct etc_plan {
   bool own_ws;
   char* ws;
   size_t ws_bytes;
-  void* kap_s;
-  double* kap_hi;
+  void* kap_s[3];      // storage precision: load-axis, a and b components (alias when isotropic)
+  double* kap_hi[3];   // float64 copies when the storage rounds the input, else nullptr
+  bool ortho;
+  double* src;         // canonical volume source, or nullptr
+  double* pin_face;    // Dirichlet values per first/last-layer face ([a][b]), or nullptr
+  double* pout_face;
   double* p;
   void *r, *w, *q, *t;
   double *lam_a, *lam_b;
@@ -140,7 +144,7 @@ DctPlan make_dct_plan(int N) {
 }
 
 struct Sizes {
-  size_t off_kap_s, off_kap_hi, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
+  size_t off_kap_s, off_kap_hi, off_src, off_faces, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
       off_part, off_st, off_hist, off_padj, total;
   int max_partials;
 };
@@ -242,7 +246,11 @@ etc_status validate(const int64_t n[3], int axis, const etc_options& o) {
   return ETC_OK;
 }
 
-Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& o) {
+struct ProblemShape {
+  bool ortho, src, faces;
+};
+
+Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& o, ProblemShape ps = {false, false, false}) {
   int nL, na, nb;
   canonical_dims(n, axis, nL, na, nb);
   Geo g{};
@@ -262,8 +270,11 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
     return o2;
   };
   const size_t V = (size_t)g.V;
-  s.off_kap_s = take(V * es);
-  s.off_kap_hi = take((o.precision == ETC_MIXED && dt == ETC_F64) ? V * sizeof(double) : 0);
+  const int ncomp = ps.ortho ? 3 : 1;
+  s.off_kap_s = take(ncomp * V * es);
+  s.off_kap_hi = take((o.precision == ETC_MIXED && dt == ETC_F64) ? ncomp * V * sizeof(double) : 0);
+  s.off_src = take(ps.src ? V * sizeof(double) : 0);
+  s.off_faces = take(ps.faces ? 2 * (size_t)g.plane * sizeof(double) : 0);
   s.off_p = take(V * sizeof(double));
   s.off_r = take(V * es);
   s.off_w = take(V * es);
@@ -305,28 +316,45 @@ void fill_lambda(std::vector<double>& lam, int N) {
 template <class S> struct Ops {
   using T = S;
 
-  static etc_status canon(etc_plan* P, const void* kappa) {
+  static Kap<S> kap(const etc_plan* P) {
+    Kap<S> k;
+    k.L = (const S*)P->kap_s[0];
+    k.A = (const S*)P->kap_s[1];
+    k.B = (const S*)P->kap_s[2];
+    k.hL = P->kap_hi[0];
+    k.hA = P->kap_hi[1];
+    k.hB = P->kap_hi[2];
+    return k;
+  }
+
+  static Rhs rhs(const etc_plan* P) { return Rhs{P->src, P->pin_face, P->pout_face}; }
+
+  // canonical copy of one user-layout array (dtype In) into dst / dst_hi
+  template <class In, class Out>
+  static etc_status canon_one(etc_plan* P, const In* src, Out* dst, double* dst_hi) {
     const Geo& g = P->g;
-    S* ks = (S*)P->kap_s;
-    if (P->in_dt == ETC_F64) {
-      const double* src = (const double*)kappa;
-      if (P->axis == 2) {
-        dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
-        k_canon_axis2<double, S><<<grid, dim3(32, 8), 0, P->stream>>>(src, ks, P->kap_hi, g);
-      } else {
-        k_canon_rows<double, S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(src, ks, P->kap_hi, P->axis, g);
-      }
+    if (P->axis == 2) {
+      dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+      k_canon_axis2<In, Out><<<grid, dim3(32, 8), 0, P->stream>>>(src, dst, dst_hi, g);
     } else {
-      const float* src = (const float*)kappa;
-      if (P->axis == 2) {
-        dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
-        k_canon_axis2<float, S><<<grid, dim3(32, 8), 0, P->stream>>>(src, ks, P->kap_hi, g);
-      } else {
-        k_canon_rows<float, S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(src, ks, P->kap_hi, P->axis, g);
-      }
+      k_canon_rows<In, Out><<<P->lc.gridStride, kThreads, 0, P->stream>>>(src, dst, dst_hi, P->axis, g);
     }
     LAUNCHCHK("canon");
-    k_extrema<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(g, ks, P->kap_hi, P->partials);
+    return ETC_OK;
+  }
+
+  static etc_status canon(etc_plan* P, const void* const comp_user[3], const double* source) {
+    for (int c = 0; c < (P->ortho ? 3 : 1); ++c) {
+      etc_status s = (P->in_dt == ETC_F64)
+                         ? canon_one<double, S>(P, (const double*)comp_user[c], (S*)P->kap_s[c], P->kap_hi[c])
+                         : canon_one<float, S>(P, (const float*)comp_user[c], (S*)P->kap_s[c], P->kap_hi[c]);
+      if (s) return s;
+    }
+    if (source) {
+      etc_status s = canon_one<double, double>(P, source, P->src, nullptr);
+      if (s) return s;
+    }
+    k_extrema<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, kap(P), P->partials);
     LAUNCHCHK("extrema");
     return ETC_OK;
   }
@@ -424,7 +452,7 @@ template <class S> struct Ops {
     const Geo& g = P->g;
     S* r = (S*)P->r;
     S* w = (S*)P->w;
-    k_init<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, r, (const S*)P->kap_s, P->kap_hi, P->partials);
+    k_init<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, r, kap(P), rhs(P), P->partials);
     LAUNCHCHK("init");
     etc_status s = fin(P, FIN_BNORM, lc.gridStride);
     if (s) return s;
@@ -437,8 +465,8 @@ template <class S> struct Ops {
         k_canon_rows<double, double><<<lc.gridStride, kThreads, 0, P->stream>>>(p0_user, P->p, nullptr, P->axis, g);
       }
       LAUNCHCHK("p0");
-      k_residual<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(g, P->p, (const S*)P->kap_s, P->kap_hi, r, P->partials,
-                                                             nullptr, 0, lc.kchunk);
+      s = residual(P, r, nullptr, 0);
+      if (s) return s;
       LAUNCHCHK("residual");
       // relative residual of the warm start
       k_fin<<<1, 1024, 0, P->stream>>>(FIN_RR0, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
@@ -455,15 +483,14 @@ template <class S> struct Ops {
     S* w = (S*)P->w;
     S* q = (S*)P->q;
     S* t = (S*)P->t;
-    const S* ks = (const S*)P->kap_s;
     const cx<T>* twa = (const cx<T>*)P->tw_a;
     const cx<T>* twb = (const cx<T>*)P->tw_b;
     etc_status s;
     // q = A w, alpha = rho / (w . q)
     timer_begin(P, 1);
-    k_apply_A<S, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(g, w, ks, q, P->partials, P->st, 1, lc.kchunk);
+    s = apply_A_launch(P, w, q, P->partials, P->st, 1);
     timer_end(P, 1);
-    LAUNCHCHK("apply_A");
+    if (s) return s;
     if ((s = fin(P, FIN_ALPHA, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
     // p += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
     timer_begin(P, 2);
@@ -475,9 +502,7 @@ template <class S> struct Ops {
     if ((s = fin(P, FIN_RR, lc.gridRows))) return s;
     if (P->prec == ETC_MIXED) {
       // replace r by the float64 true residual when requested, and redo DCT_b
-      k_residual<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(g, P->p, ks, P->kap_hi, r, P->partials, P->st, 2,
-                                                             lc.kchunk);
-      LAUNCHCHK("residual");
+      if ((s = residual(P, r, P->st, 2))) return s;
       if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
       k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
           g, P->dpb, twb, r, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
@@ -507,14 +532,13 @@ template <class S> struct Ops {
 
   static etc_status keff(etc_plan* P, bool energy) {
     const LaunchCfg& lc = P->lc;
-    const S* ks = (const S*)P->kap_s;
-    k_keff<S><<<lc.gridKeff, kThreads, 0, P->stream>>>(P->g, P->p, ks, P->kap_hi, P->partials);
+    k_keff<S><<<lc.gridKeff, kThreads, 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), P->partials);
     LAUNCHCHK("keff");
     k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC0, P->partials, lc.gridKeff, P->st, P->hist);
     k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC1, P->partials + lc.gridKeff, lc.gridKeff, P->st, P->hist);
     LAUNCHCHK("fin");
     if (energy) {
-      k_energy<S><<<lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, ks, P->kap_hi, P->partials);
+      k_energy<S><<<lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), P->partials);
       LAUNCHCHK("energy");
       k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC2, P->partials, lc.gridStride, P->st, P->hist);
       LAUNCHCHK("fin");
@@ -523,17 +547,37 @@ template <class S> struct Ops {
   }
 
   static etc_status grad(etc_plan* P, double* out_user, double c) {
-    k_grad<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, P->padj, (const S*)P->kap_s, P->kap_hi, c,
-                                                             P->axis, out_user);
+    k_grad<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, P->padj, kap(P), c, P->axis, out_user);
     LAUNCHCHK("grad");
+    return ETC_OK;
+  }
+
+  static etc_status apply_A_launch(etc_plan* P, const S* x, S* y, double* partials, const DevState* st, int gate) {
+    const LaunchCfg& lc = P->lc;
+    if (P->ortho)
+      k_apply_A<S, S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
+    else
+      k_apply_A<S, S, false><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
+    LAUNCHCHK("apply_A");
+    return ETC_OK;
+  }
+
+  static etc_status residual(etc_plan* P, S* r, const DevState* st, int gate) {
+    const LaunchCfg& lc = P->lc;
+    if (P->ortho)
+      k_residual<S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
+                                                                   lc.kchunk);
+    else
+      k_residual<S, false><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st,
+                                                                    gate, lc.kchunk);
+    LAUNCHCHK("residual");
     return ETC_OK;
   }
 
   static etc_status apply_A(etc_plan* P, const void* x, void* y, bool dot) {
     const LaunchCfg& lc = P->lc;
-    k_apply_A<S, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, (const S*)x, (const S*)P->kap_s, (S*)y,
-                                                            dot ? P->partials : nullptr, nullptr, 0, lc.kchunk);
-    LAUNCHCHK("apply_A");
+    etc_status s = apply_A_launch(P, (const S*)x, (S*)y, dot ? P->partials : nullptr, nullptr, 0);
+    if (s) return s;
     if (dot) {
       k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC3, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
       LAUNCHCHK("fin");
@@ -565,22 +609,52 @@ const char* etc_last_error(void) { return g_err.c_str(); }
 
 const char* etc_version(void) { return "etc-mi355x 0.1 (gfx950)"; }
 
-etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const etc_options* opt, size_t* bytes) {
+static ProblemShape shape_of(const etc_problem* pr) {
+  ProblemShape ps{false, false, false};
+  if (pr) {
+    ps.ortho = pr->kappa[1] != nullptr || pr->kappa[2] != nullptr;
+    ps.src = pr->source != nullptr;
+    ps.faces = pr->p_in_face != nullptr || pr->p_out_face != nullptr;
+  }
+  return ps;
+}
+
+etc_status etc_workspace_size_ex(const etc_problem* pr, const int64_t n[3], etc_dtype dt, int axis,
+                                 const etc_options* opt, size_t* bytes) {
   etc_options o;
   if (opt) o = *opt;
   else etc_options_default(&o);
   if (!bytes) return fail(ETC_E_INVALID, "bytes is NULL");
   etc_status s = validate(n, axis, o);
   if (s) return s;
-  *bytes = plan_sizes(n, axis, dt, o).total;
+  *bytes = plan_sizes(n, axis, dt, o, shape_of(pr)).total;
   return ETC_OK;
+}
+
+etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const etc_options* opt, size_t* bytes) {
+  return etc_workspace_size_ex(nullptr, n, dt, axis, opt, bytes);
 }
 
 etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
                      const etc_options* opt, etc_plan** out) {
+  etc_problem pr;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.kappa[0] = kappa;
+  return etc_setup_ex(&pr, dt, n, bc, axis, opt, out);
+}
+
+etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                        const etc_options* opt, etc_plan** out) {
   if (!out) return fail(ETC_E_INVALID, "plan is NULL");
   *out = nullptr;
-  if (!kappa) return fail(ETC_E_INVALID, "kappa is NULL");
+  if (!pr) return fail(ETC_E_INVALID, "problem is NULL");
+  const ProblemShape ps = shape_of(pr);
+  if (ps.ortho) {
+    for (int d = 0; d < 3; ++d)
+      if (!pr->kappa[d]) return fail(ETC_E_INVALID, "an orthotropic problem needs all three kappa components");
+  } else if (!pr->kappa[0]) {
+    return fail(ETC_E_INVALID, "kappa is NULL");
+  }
   if (dt != ETC_F64 && dt != ETC_F32) return fail(ETC_E_INVALID, "bad dtype");
   etc_options o;
   if (opt) o = *opt;
@@ -626,7 +700,9 @@ etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc
   P->dpb = make_dct_plan(nb);
   P->lc = make_launch(g, P->dpa, P->dpb, es);
 
-  Sizes sz = plan_sizes(n, axis, dt, o);
+  if (o.want_grad && (ps.ortho || ps.src || ps.faces))
+    return fail(ETC_E_UNSUPPORTED, "etc_grad covers isotropic kappa with constant Dirichlet data only");
+  Sizes sz = plan_sizes(n, axis, dt, o, ps);
   P->max_partials = sz.max_partials;
   if (o.workspace) {
     if (o.workspace_bytes < sz.total) {
@@ -650,8 +726,19 @@ etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc
     return fail(ETC_E_NOMEM, "pinned host allocation failed");
   }
   char* b = P->ws;
-  P->kap_s = b + sz.off_kap_s;
-  P->kap_hi = (P->prec == ETC_MIXED && dt == ETC_F64) ? (double*)(b + sz.off_kap_hi) : nullptr;
+  P->ortho = ps.ortho;
+  {
+    const size_t vbytes = (size_t)g.V * es;
+    const bool hi = (P->prec == ETC_MIXED && dt == ETC_F64);
+    for (int c = 0; c < 3; ++c) {
+      const int cc = ps.ortho ? c : 0;
+      P->kap_s[c] = b + sz.off_kap_s + cc * vbytes;
+      P->kap_hi[c] = hi ? (double*)(b + sz.off_kap_hi) + (size_t)cc * g.V : nullptr;
+    }
+  }
+  P->src = ps.src ? (double*)(b + sz.off_src) : nullptr;
+  P->pin_face = ps.faces ? (double*)(b + sz.off_faces) : nullptr;
+  P->pout_face = ps.faces ? (double*)(b + sz.off_faces) + g.plane : nullptr;
   P->p = (double*)(b + sz.off_p);
   P->r = b + sz.off_r;
   P->w = b + sz.off_w;
@@ -674,7 +761,32 @@ etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc
   // canonical copy + extrema
   s = (P->prec == ETC_MIXED) ? Ops<float>::lds_limits(P) : Ops<double>::lds_limits(P);
   if (s) return bail(s);
-  s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, kappa) : Ops<double>::canon(P, kappa);
+  {
+    // user component order -> canonical (load axis, a, b)
+    const void* comp[3] = {pr->kappa[0], pr->kappa[0], pr->kappa[0]};
+    if (ps.ortho) {
+      int order[3] = {axis, 0, 0}, c = 1;
+      for (int d = 0; d < 3; ++d)
+        if (d != axis) order[c++] = d;
+      for (int d = 0; d < 3; ++d) comp[d] = pr->kappa[order[d]];
+    }
+    s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source) : Ops<double>::canon(P, comp, pr->source);
+  }
+  if (s) return bail(s);
+  if (ps.faces) {
+    // face data: [a][b] over the transverse axes in user order (constant pair where NULL)
+    std::vector<double> pin((size_t)g.plane, bc.p_in), pout((size_t)g.plane, bc.p_out);
+    if (hipMemcpyAsync(P->pin_face, pin.data(), pin.size() * sizeof(double), hipMemcpyHostToDevice, P->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->pout_face, pout.data(), pout.size() * sizeof(double), hipMemcpyHostToDevice, P->stream) !=
+            hipSuccess ||
+        (pr->p_in_face && hipMemcpyAsync(P->pin_face, pr->p_in_face, (size_t)g.plane * sizeof(double),
+                                         hipMemcpyDeviceToDevice, P->stream) != hipSuccess) ||
+        (pr->p_out_face && hipMemcpyAsync(P->pout_face, pr->p_out_face, (size_t)g.plane * sizeof(double),
+                                          hipMemcpyDeviceToDevice, P->stream) != hipSuccess) ||
+        hipStreamSynchronize(P->stream) != hipSuccess)
+      return bail(fail(ETC_E_HIP, "copying the Dirichlet face data failed"));
+  }
   if (s) return bail(s);
   std::vector<double> part((size_t)P->lc.gridStride * 12);
   if (hipMemcpyAsync(part.data(), P->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream) !=

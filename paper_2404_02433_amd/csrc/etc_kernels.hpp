@@ -21,11 +21,40 @@ __device__ __forceinline__ bool gated_out(const DevState* st, int gate) {
   return false;
 }
 
-__device__ __forceinline__ double kap_at(const float* ks, const double* kh, int64_t i) {
-  return kh ? kh[i] : (double)ks[i];
-}
-__device__ __forceinline__ double kap_at(const double* ks, const double* kh, int64_t i) {
-  return kh ? kh[i] : ks[i];
+// Conductivity views: storage-precision arrays of the load-axis component L
+// and the two transverse components A, B (all three alias one array for an
+// isotropic medium), and float64 copies when the storage rounds the input
+// (null otherwise).
+template <class S> struct Kap {
+  const S* L;
+  const S* A;
+  const S* B;
+  const double* hL;
+  const double* hA;
+  const double* hB;
+  __device__ __forceinline__ double dL(int64_t i) const { return hL ? hL[i] : (double)L[i]; }
+  __device__ __forceinline__ double dA(int64_t i) const { return hA ? hA[i] : (double)A[i]; }
+  __device__ __forceinline__ double dB(int64_t i) const { return hB ? hB[i] : (double)B[i]; }
+};
+
+// Right-hand-side data beyond the constant Dirichlet pair, all nullable:
+// a volume source per voxel (canonical layout) and Dirichlet values per face
+// of the first and last load layers ([a][b]).
+struct Rhs {
+  const double* src;
+  const double* pin;
+  const double* pout;
+};
+
+// b at canonical index i (load layer k, transverse offset col): the source
+// plus 2 kappa~ p_D on the Dirichlet layers (eq:flux with face data p_D).
+template <class S>
+__device__ __forceinline__ double rhs_at(const Geo& g, const Kap<S>& kp, const Rhs& rh, int64_t i, int64_t k,
+                                         int64_t col) {
+  double bv = rh.src ? rh.src[i] : 0.0;
+  if (k == 0) bv += 2.0 * g.fL * kp.dL(i) * (rh.pin ? rh.pin[col] : g.p_in);
+  if (k == g.nL - 1) bv += 2.0 * g.fL * kp.dL(i) * (rh.pout ? rh.pout[col] : g.p_out);
+  return bv;
 }
 
 // ===================================================================== setup
@@ -98,8 +127,7 @@ __global__ void k_decanon_axis2(const double* __restrict__ src, double* __restri
 // count of invalid conductivities (<= 0, NaN, Inf).  12 partials per block:
 // [minL maxL mina maxa minb maxb minin maxin minout maxout invalid unused].
 template <class S>
-__global__ __launch_bounds__(256) void k_extrema(Geo g, const S* __restrict__ ks, const double* __restrict__ kh,
-                                                 double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __restrict__ partials) {
   double mn[5], mx[5];
   for (int f = 0; f < 5; ++f) {
     mn[f] = __builtin_huge_val();
@@ -110,20 +138,20 @@ __global__ __launch_bounds__(256) void k_extrema(Geo g, const S* __restrict__ ks
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
     const int64_t k = i / g.plane, rem = i - k * g.plane;
     const int64_t a = rem / g.nb, b = rem - a * g.nb;
-    const double kc = kap_at(ks, kh, i);
-    if (!(kc > 0.0) || !isfinite(kc)) bad += 1.0;
+    const double kc = kp.dL(i), ka = kp.dA(i), kb = kp.dB(i);
+    if (!(kc > 0.0) || !isfinite(kc) || !(ka > 0.0) || !isfinite(ka) || !(kb > 0.0) || !isfinite(kb)) bad += 1.0;
     if (k > 0) {
-      const double t = g.fL * harm(kc, kap_at(ks, kh, i - g.plane));
+      const double t = g.fL * harm(kc, kp.dL(i - g.plane));
       mn[0] = fmin(mn[0], t);
       mx[0] = fmax(mx[0], t);
     }
     if (a > 0) {
-      const double t = g.fa * harm(kc, kap_at(ks, kh, i - g.nb));
+      const double t = g.fa * harm(ka, kp.dA(i - g.nb));
       mn[1] = fmin(mn[1], t);
       mx[1] = fmax(mx[1], t);
     }
     if (b > 0) {
-      const double t = g.fb * harm(kc, kap_at(ks, kh, i - 1));
+      const double t = g.fb * harm(kb, kp.dB(i - 1));
       mn[2] = fmin(mn[2], t);
       mx[2] = fmax(mx[2], t);
     }
@@ -164,20 +192,17 @@ __global__ __launch_bounds__(256) void k_extrema(Geo g, const S* __restrict__ ks
   }
 }
 
-// p = 0, r = b (2 kappa~ p_in on the first load layer, 2 kappa~ p_out on the
-// last), partial ||b||^2.
+// p = 0, r = b (source plus 2 kappa~ p_in on the first load layer and
+// 2 kappa~ p_out on the last), partial ||b||^2.
 template <class S>
-__global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* __restrict__ r,
-                                              const S* __restrict__ ks, const double* __restrict__ kh,
+__global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* __restrict__ r, Kap<S> kp, Rhs rh,
                                               double* __restrict__ partials) {
   __shared__ double red[16];
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t last = (int64_t)(g.nL - 1) * g.plane;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    double bv = 0.0;
-    if (i < g.plane) bv = 2.0 * g.fL * kap_at(ks, kh, i) * g.p_in;
-    if (i >= last) bv = 2.0 * g.fL * kap_at(ks, kh, i) * g.p_out;
+    const int64_t k = i / g.plane, col = i - k * g.plane;
+    const double bv = rhs_at(g, kp, rh, i, k, col);
     p[i] = 0.0;
     const S bs = (S)bv;
     r[i] = bs;
@@ -192,10 +217,10 @@ __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* 
 // with the partial w . q of each block.  Block (64, 4) covers 64 b x 4 a
 // columns and marches along k over `kchunk` planes keeping the k-1, k, k+1
 // values in registers; lateral neighbours come through the caches.
-template <class S, class C>
-__global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w, const S* __restrict__ ks,
-                                                 S* __restrict__ q, double* __restrict__ partials,
-                                                 const DevState* __restrict__ st, int gate, int kchunk) {
+template <class S, class C, bool ORTHO>
+__global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w, Kap<S> kp, S* __restrict__ q,
+                                                 double* __restrict__ partials, const DevState* __restrict__ st,
+                                                 int gate, int kchunk) {
   if (gated_out(st, gate)) return;
   __shared__ double red[16];
   const int b = blockIdx.x * 64 + threadIdx.x;
@@ -203,6 +228,9 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
   const int k0 = blockIdx.z * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
   const bool valid = (a < g.na) && (b < g.nb);
+  const S* __restrict__ ks = kp.L;
+  const S* __restrict__ ka = ORTHO ? kp.A : kp.L;
+  const S* __restrict__ kb = ORTHO ? kp.B : kp.L;
   double acc = 0.0;
   if (valid) {
     const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
@@ -215,27 +243,28 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
       km = (C)ks[i - g.plane];
     }
     for (int k = k0; k < k1; ++k, i += g.plane) {
-      C wp = C(0), kp = C(1);
+      C wp = C(0), kpp = C(1);
       if (k + 1 < g.nL) {
         wp = (C)w[i + g.plane];
-        kp = (C)ks[i + g.plane];
+        kpp = (C)ks[i + g.plane];
       }
       C qv;
       if (k > 0) qv = fL * harm(kc, km) * (wc - wm);
       else qv = C(2) * fL * kc * wc;
-      if (k + 1 < g.nL) qv += fL * harm(kc, kp) * (wc - wp);
+      if (k + 1 < g.nL) qv += fL * harm(kc, kpp) * (wc - wp);
       else qv += C(2) * fL * kc * wc;
-      if (a > 0) qv += fa * harm(kc, (C)ks[i - g.nb]) * (wc - (C)w[i - g.nb]);
-      if (a + 1 < g.na) qv += fa * harm(kc, (C)ks[i + g.nb]) * (wc - (C)w[i + g.nb]);
-      if (b > 0) qv += fb * harm(kc, (C)ks[i - 1]) * (wc - (C)w[i - 1]);
-      if (b + 1 < g.nb) qv += fb * harm(kc, (C)ks[i + 1]) * (wc - (C)w[i + 1]);
+      const C kac = ORTHO ? (C)ka[i] : kc, kbc = ORTHO ? (C)kb[i] : kc;
+      if (a > 0) qv += fa * harm(kac, (C)ka[i - g.nb]) * (wc - (C)w[i - g.nb]);
+      if (a + 1 < g.na) qv += fa * harm(kac, (C)ka[i + g.nb]) * (wc - (C)w[i + g.nb]);
+      if (b > 0) qv += fb * harm(kbc, (C)kb[i - 1]) * (wc - (C)w[i - 1]);
+      if (b + 1 < g.nb) qv += fb * harm(kbc, (C)kb[i + 1]) * (wc - (C)w[i + 1]);
       const S qs = (S)qv;
       q[i] = qs;
       acc += (double)wc * (double)qs;
       wm = wc;
       km = kc;
       wc = wp;
-      kc = kp;
+      kc = kpp;
     }
   }
   if (partials) {
@@ -246,11 +275,10 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
 
 // r = b - A p in double arithmetic (p double, kappa at its input precision),
 // stored at S precision, with the partial ||r||^2.  Same tiling as k_apply_A.
-template <class S>
-__global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restrict__ p, const S* __restrict__ ks,
-                                                  const double* __restrict__ kh, S* __restrict__ r,
-                                                  double* __restrict__ partials, const DevState* __restrict__ st,
-                                                  int gate, int kchunk) {
+template <class S, bool ORTHO>
+__global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
+                                                  S* __restrict__ r, double* __restrict__ partials,
+                                                  const DevState* __restrict__ st, int gate, int kchunk) {
   if (gated_out(st, gate)) return;
   __shared__ double red[16];
   const int b = blockIdx.x * 64 + threadIdx.x;
@@ -262,40 +290,42 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
   if (valid) {
     const int64_t col = (int64_t)a * g.nb + b;
     int64_t i = (int64_t)k0 * g.plane + col;
-    double pc = p[i], kc = kap_at(ks, kh, i);
+    double pc = p[i], kc = kp.dL(i);
     double pm = 0.0, km = 1.0;
     if (k0 > 0) {
       pm = p[i - g.plane];
-      km = kap_at(ks, kh, i - g.plane);
+      km = kp.dL(i - g.plane);
     }
     for (int k = k0; k < k1; ++k, i += g.plane) {
-      double pp = 0.0, kp = 1.0;
+      double pp = 0.0, kpp = 1.0;
       if (k + 1 < g.nL) {
         pp = p[i + g.plane];
-        kp = kap_at(ks, kh, i + g.plane);
+        kpp = kp.dL(i + g.plane);
       }
-      double qv = 0.0, bv = 0.0;
+      double qv = 0.0;
       if (k > 0) qv = g.fL * harm(kc, km) * (pc - pm);
-      else {
-        qv = 2.0 * g.fL * kc * pc;
-        bv = 2.0 * g.fL * kc * g.p_in;
+      else qv = 2.0 * g.fL * kc * pc;
+      if (k + 1 < g.nL) qv += g.fL * harm(kc, kpp) * (pc - pp);
+      else qv += 2.0 * g.fL * kc * pc;
+      const double kac = ORTHO ? kp.dA(i) : kc, kbc = ORTHO ? kp.dB(i) : kc;
+      if (ORTHO) {
+        if (a > 0) qv += g.fa * harm(kac, kp.dA(i - g.nb)) * (pc - p[i - g.nb]);
+        if (a + 1 < g.na) qv += g.fa * harm(kac, kp.dA(i + g.nb)) * (pc - p[i + g.nb]);
+        if (b > 0) qv += g.fb * harm(kbc, kp.dB(i - 1)) * (pc - p[i - 1]);
+        if (b + 1 < g.nb) qv += g.fb * harm(kbc, kp.dB(i + 1)) * (pc - p[i + 1]);
+      } else {
+        if (a > 0) qv += g.fa * harm(kc, kp.dL(i - g.nb)) * (pc - p[i - g.nb]);
+        if (a + 1 < g.na) qv += g.fa * harm(kc, kp.dL(i + g.nb)) * (pc - p[i + g.nb]);
+        if (b > 0) qv += g.fb * harm(kc, kp.dL(i - 1)) * (pc - p[i - 1]);
+        if (b + 1 < g.nb) qv += g.fb * harm(kc, kp.dL(i + 1)) * (pc - p[i + 1]);
       }
-      if (k + 1 < g.nL) qv += g.fL * harm(kc, kp) * (pc - pp);
-      else {
-        qv += 2.0 * g.fL * kc * pc;
-        bv += 2.0 * g.fL * kc * g.p_out;
-      }
-      if (a > 0) qv += g.fa * harm(kc, kap_at(ks, kh, i - g.nb)) * (pc - p[i - g.nb]);
-      if (a + 1 < g.na) qv += g.fa * harm(kc, kap_at(ks, kh, i + g.nb)) * (pc - p[i + g.nb]);
-      if (b > 0) qv += g.fb * harm(kc, kap_at(ks, kh, i - 1)) * (pc - p[i - 1]);
-      if (b + 1 < g.nb) qv += g.fb * harm(kc, kap_at(ks, kh, i + 1)) * (pc - p[i + 1]);
-      const S rs = (S)(bv - qv);
+      const S rs = (S)(rhs_at(g, kp, rh, i, k, col) - qv);
       r[i] = rs;
       acc += (double)rs * (double)rs;
       pm = pc;
       km = kc;
       pc = pp;
-      kc = kp;
+      kc = kpp;
     }
   }
   const double s = block_sum(acc, red);
@@ -902,14 +932,15 @@ __global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__
 // Flux sums over the two Dirichlet layers: comp 0 = sum 2 kappa (p_last -
 // p_out), comp 1 = sum 2 kappa (p_in - p_first).  Partials [2][nblk].
 template <class S>
-__global__ __launch_bounds__(256) void k_keff(Geo g, const double* __restrict__ p, const S* __restrict__ ks,
-                                              const double* __restrict__ kh, double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_keff(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
+                                              double* __restrict__ partials) {
   __shared__ double red[16];
   double ao = 0.0, ai = 0.0;
   const int64_t last = (int64_t)(g.nL - 1) * g.plane;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.plane; i += (int64_t)gridDim.x * blockDim.x) {
-    ao += 2.0 * kap_at(ks, kh, last + i) * (p[last + i] - g.p_out);
-    ai += 2.0 * kap_at(ks, kh, i) * (g.p_in - p[i]);
+    const double po = rh.pout ? rh.pout[i] : g.p_out, pi = rh.pin ? rh.pin[i] : g.p_in;
+    ao += 2.0 * kp.dL(last + i) * (p[last + i] - po);
+    ai += 2.0 * kp.dL(i) * (pi - p[i]);
   }
   const double so = block_sum(ao, red);
   const double si = block_sum(ai, red);
@@ -922,33 +953,33 @@ __global__ __launch_bounds__(256) void k_keff(Geo g, const double* __restrict__ 
 // Dissipation sum over every face (internal faces counted once from their
 // upper cell, plus the Dirichlet faces), double arithmetic.
 template <class S>
-__global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict__ p, const S* __restrict__ ks,
-                                                const double* __restrict__ kh, double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
+                                                double* __restrict__ partials) {
   __shared__ double red[16];
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
     const int64_t k = i / g.plane, rem = i - k * g.plane;
     const int64_t a = rem / g.nb, b = rem - a * g.nb;
-    const double kc = kap_at(ks, kh, i), pc = p[i];
+    const double kc = kp.dL(i), pc = p[i];
     if (k > 0) {
       const double d = pc - p[i - g.plane];
-      acc += g.fL * harm(kc, kap_at(ks, kh, i - g.plane)) * d * d;
+      acc += g.fL * harm(kc, kp.dL(i - g.plane)) * d * d;
     } else {
-      const double d = pc - g.p_in;
+      const double d = pc - (rh.pin ? rh.pin[rem] : g.p_in);
       acc += 2.0 * g.fL * kc * d * d;
     }
     if (k == g.nL - 1) {
-      const double d = pc - g.p_out;
+      const double d = pc - (rh.pout ? rh.pout[rem] : g.p_out);
       acc += 2.0 * g.fL * kc * d * d;
     }
     if (a > 0) {
       const double d = pc - p[i - g.nb];
-      acc += g.fa * harm(kc, kap_at(ks, kh, i - g.nb)) * d * d;
+      acc += g.fa * harm(kp.dA(i), kp.dA(i - g.nb)) * d * d;
     }
     if (b > 0) {
       const double d = pc - p[i - 1];
-      acc += g.fb * harm(kc, kap_at(ks, kh, i - 1)) * d * d;
+      acc += g.fb * harm(kp.dB(i), kp.dB(i - 1)) * d * d;
     }
   }
   const double s = block_sum(acc, red);
@@ -967,17 +998,16 @@ __global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict_
 // user layout of load axis `axis`; double arithmetic.
 template <class S>
 __global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ p, const double* __restrict__ phi,
-                                              const S* __restrict__ ks, const double* __restrict__ kh, double c,
-                                              int axis, double* __restrict__ out) {
+                                              Kap<S> kp, double c, int axis, double* __restrict__ out) {
   const double lsc = c / g.fL;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
     const int64_t k = i / g.plane, rem = i - k * g.plane;
     const int64_t a = rem / g.nb, b = rem - a * g.nb;
-    const double kv = kap_at(ks, kh, i), pv = p[i], lv = lsc * phi[i];
+    const double kv = kp.dL(i), pv = p[i], lv = lsc * phi[i];
     double gv = 0.0;
     auto face = [&](int64_t n, double f) {
-      const double kn = kap_at(ks, kh, n);
+      const double kn = kp.dL(n);
       const double sden = kv + kn;
       gv -= f * 2.0 * kn * kn / (sden * sden) * (pv - p[n]) * (lv - lsc * phi[n]);
     };

@@ -289,3 +289,57 @@ def test_grad_requires_want_grad():
         etc.etc_grad(plan)
     assert e.value.status == -5
     plan.close()
+
+
+# ------------------------------------------- orthotropic kappa, sources, faces
+from problems import smooth_problem  # noqa: E402
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [32, 64])
+def test_smooth_orthotropic_table1_on_gpu(n, precision):
+    """tab:smooth: L2 error of the TPFA solution of the smooth orthotropic
+    problem (source term, Dirichlet data varying over the faces)."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table1_smooth.json")) as f:
+        t1 = json.load(f)
+    comps, src, pin, pout, exact = smooth_problem(n)
+    rtol = 1e-9 if precision == "fp64" else 1e-7
+    plan = etc.etc_setup([dev(c) for c in comps], 2, precision=precision, rtol=rtol, L=(1.0, 1.0, 1.0),
+                         source=dev(src), p_in_face=dev(pin), p_out_face=dev(pout))
+    out = etc.etc_solve(plan)
+    p = etc.etc_get_solution(plan).cpu().numpy()
+    plan.close()
+    err = math.sqrt(np.sum((p - exact) ** 2) / n ** 3)
+    ref = t1["l2_error_rtol_1e-9"][t1["n"].index(n)]
+    assert out["status"] == "ok"
+    assert abs(err - ref) <= 0.006 * ref, (n, err, ref)
+    if precision == "fp64":
+        assert out["iters"] == t1["iters_rtol_1e-9"][t1["n"].index(n)]
+
+
+def test_orthotropic_operator_and_solution_match_oracle():
+    shape = (21, 17, 26)
+    rng = np.random.default_rng(9)
+    comps = [np.exp(0.6 * rng.standard_normal(shape)) for _ in range(3)]
+    src = rng.standard_normal(shape)
+    pin = 1.0 + 0.1 * rng.standard_normal((shape[0], shape[2]))
+    pout = -0.5 + 0.1 * rng.standard_normal((shape[0], shape[2]))
+    axis = 1
+    pb = O.make_problem(None, axis, pin, pout, L=(2.0, 1.0, 1.5), components=comps, source=src)
+    plan = etc.etc_setup([dev(c) for c in comps], axis, p_in=1.0, p_out=-0.5, rtol=1e-12, L=(2.0, 1.0, 1.5),
+                         source=dev(src), p_in_face=dev(pin), p_out_face=dev(pout))
+    x = rng.standard_normal(pb.shape)
+    y = etc.etc_apply_A(plan, dev(x)).cpu().numpy()
+    ref = O.apply_A(pb, x)
+    assert np.abs(y - ref).max() < 1e-13 * np.abs(ref).max()
+    z = etc.etc_apply_Minv(plan, dev(x)).cpu().numpy()
+    zref = O.apply_Aref_inv(x, O.kref_mid(pb))
+    assert np.abs(z - zref).max() < 1e-11 * np.abs(zref).max()
+    etc.etc_solve(plan)
+    p = etc.etc_get_solution(plan).cpu().numpy()
+    pref = O.decanonical(O.pcg(pb, rtol=1e-13).p, axis)
+    assert np.abs(p - pref).max() < 1e-9 * np.abs(pref).max()
+    plan.close()

@@ -18,6 +18,7 @@ import scipy.optimize
 
 import rvegen
 from oracle import etc_oracle as O
+from problems import smooth_problem
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -303,19 +304,6 @@ def test_axis_choice_is_a_relabelling():
 
 
 # --------------------------------------------------------------- paper's Table 1
-def smooth_problem(n):
-    """The smooth orthotropic manufactured solution of tab:smooth, sampled at
-    cell centres (conductivity, source) and Dirichlet face centres."""
-    c = (np.arange(n) + 0.5) / n
-    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
-    kx, ky, kz = np.cos(np.pi * Y) + 2, 2 * np.exp(Z), 3 * np.cos(np.pi * X) + 4
-    exact = np.cos(np.pi * X) * np.cos(np.pi * Y) * np.exp(Z)
-    # f = -div(K grad p) for this K and p (each component is constant along its own axis)
-    f = exact * (np.pi ** 2 * (np.cos(np.pi * Y) + 2 + 2 * np.exp(Z)) - 3 * np.cos(np.pi * X) - 4)
-    face = np.cos(np.pi * c)[:, None] * np.cos(np.pi * c)[None, :]
-    return (kx, ky, kz), f, face * 1.0, face * np.e, exact
-
-
 @pytest.mark.parametrize("n", [32, 64])
 def test_smooth_orthotropic_matches_table1(n):
     with open(os.path.join(GOLD, "table1_smooth.json")) as f:
