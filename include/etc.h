@@ -68,6 +68,10 @@ typedef enum { ETC_FP64 = 0, ETC_MIXED = 1 } etc_precision;
  * eq:linear programming); ONE = all 1 (the paper's "one"); USER = kref_user. */
 typedef enum { ETC_KREF_MID = 0, ETC_KREF_ONE = 1, ETC_KREF_USER = 2 } etc_kref_mode;
 
+/* Preconditioner: DCT = the reference-medium solve of alg:solve ref;
+ * NONE = plain CG (z = r), for the comparison behind prop:cond. */
+typedef enum { ETC_PC_DCT = 0, ETC_PC_NONE = 1 } etc_precond;
+
 /* Dirichlet pair on the faces normal to the load axis (p_in at index 0). */
 typedef struct {
   double p_in, p_out;
@@ -86,6 +90,7 @@ typedef struct {
   void* workspace;       /* optional caller-owned device memory (>= etc_workspace_size) */
   size_t workspace_bytes;
   int want_grad;         /* 1: reserve the adjoint state for etc_grad (8 bytes per voxel) */
+  etc_precond precond;   /* default ETC_PC_DCT */
 } etc_options;
 
 typedef struct {

@@ -57,6 +57,7 @@ class _Options(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("want_grad", ctypes.c_int),
+        ("precond", ctypes.c_int),
     ]
 
 
@@ -153,7 +154,7 @@ def _torch():
 
 
 def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_every=8, kref="mid",
-             kref_user=None, L=None, stream=None, want_grad=False) -> _Options:
+             kref_user=None, L=None, stream=None, want_grad=False, precond="dct") -> _Options:
     lib = load_library()
     o = _Options()
     lib.etc_options_default(ctypes.byref(o))
@@ -171,6 +172,7 @@ def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_e
             o.L[d] = float(L[d])
     o.stream = stream
     o.want_grad = 1 if want_grad else 0
+    o.precond = {"dct": 0, "none": 1}[precond]
     return o
 
 
@@ -223,7 +225,7 @@ class Plan:
 def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
               rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
               kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, source=None,
-              p_in_face=None, p_out_face=None) -> Plan:
+              p_in_face=None, p_out_face=None, precond: str = "dct") -> Plan:
     """Preparation phase on device data (user layout, load axis ``axis``).
 
     ``kappa`` is one tensor (isotropic) or a sequence of three tensors, the
@@ -246,7 +248,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
     dtype = "float64" if k0.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(k0.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad)
+                 want_grad, precond)
     n = _dims(k0.shape)
     pr = _Problem()
     keep = list(comps)

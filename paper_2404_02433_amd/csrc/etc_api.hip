@@ -234,6 +234,7 @@ etc_status validate(const int64_t n[3], int axis, const etc_options& o) {
   if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(ETC_E_INVALID, "rtol must be > 0");
   if (o.max_iter < 0) return fail(ETC_E_INVALID, "max_iter must be >= 0");
   if (o.precision != ETC_FP64 && o.precision != ETC_MIXED) return fail(ETC_E_INVALID, "bad precision");
+  if (o.precond != ETC_PC_DCT && o.precond != ETC_PC_NONE) return fail(ETC_E_INVALID, "bad preconditioner");
   if (o.kref_mode == ETC_KREF_USER)
     for (int i = 0; i < 5; ++i)
       if (!(o.kref_user[i] > 0.0) || !std::isfinite(o.kref_user[i]))
@@ -472,11 +473,45 @@ template <class S> struct Ops {
       k_fin<<<1, 1024, 0, P->stream>>>(FIN_RR0, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
       LAUNCHCHK("fin");
     }
+    if (P->opt.precond == ETC_PC_NONE) {
+      k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
+      LAUNCHCHK("norm2");
+      if ((s = fin(P, FIN_RHO0, lc.gridStride))) return s;
+      k_dir_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, w, P->st, 1);
+      LAUNCHCHK("dir");
+      return ETC_OK;
+    }
     return precond(P, r, w, 0, P->st, 1, FIN_RHO0);
+  }
+
+  // One pass of plain CG (z = r).
+  static etc_status iteration_plain(etc_plan* P) {
+    const LaunchCfg& lc = P->lc;
+    const Geo& g = P->g;
+    S* r = (S*)P->r;
+    S* w = (S*)P->w;
+    S* q = (S*)P->q;
+    etc_status s;
+    if ((s = apply_A_launch(P, w, q, P->partials, P->st, 1))) return s;
+    if ((s = fin(P, FIN_ALPHA, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+    k_update_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, w, r, q, P->partials, P->st);
+    LAUNCHCHK("update");
+    if ((s = fin(P, FIN_RR, lc.gridStride))) return s;
+    if (P->prec == ETC_MIXED) {
+      if ((s = residual(P, r, P->st, 2))) return s;
+      if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+    }
+    k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
+    LAUNCHCHK("norm2");
+    if ((s = fin(P, FIN_BETA, lc.gridStride))) return s;
+    k_dir_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, w, P->st, 0);
+    LAUNCHCHK("dir");
+    return ETC_OK;
   }
 
   // One PCG pass (alg:pcg loop body) on the device.
   static etc_status iteration(etc_plan* P) {
+    if (P->opt.precond == ETC_PC_NONE) return iteration_plain(P);
     const LaunchCfg& lc = P->lc;
     const Geo& g = P->g;
     S* r = (S*)P->r;
@@ -486,6 +521,7 @@ template <class S> struct Ops {
     const cx<T>* twa = (const cx<T>*)P->tw_a;
     const cx<T>* twb = (const cx<T>*)P->tw_b;
     etc_status s;
+    (void)g;
     // q = A w, alpha = rho / (w . q)
     timer_begin(P, 1);
     s = apply_A_launch(P, w, q, P->partials, P->st, 1);
@@ -603,6 +639,7 @@ void etc_options_default(etc_options* o) {
   o->poll_every = 8;
   o->stream = nullptr;
   o->want_grad = 0;
+  o->precond = ETC_PC_DCT;
 }
 
 const char* etc_last_error(void) { return g_err.c_str(); }
@@ -1017,6 +1054,11 @@ etc_status etc_apply_A(etc_plan* P, const void* x, void* y, double* xAx) {
 etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
   if (!P || !r || !z) return fail(ETC_E_INVALID, "NULL argument");
   if (r == z) return fail(ETC_E_INVALID, "r and z must not alias");
+  if (P->opt.precond == ETC_PC_NONE) {
+    HIPCHK(hipMemcpyAsync(z, r, (size_t)P->g.V * elt_size(P->prec), hipMemcpyDeviceToDevice, P->stream));
+    if (rz) return fail(ETC_E_UNSUPPORTED, "no dot without a preconditioner");
+    return ETC_OK;
+  }
   etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::precond(P, (const float*)r, (float*)z, 0, P->st, 0, FIN_ACC3)
                                         : Ops<double>::precond(P, (const double*)r, (double*)z, 0, P->st, 0, FIN_ACC3);
   if (s) return s;

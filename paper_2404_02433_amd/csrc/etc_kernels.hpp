@@ -1024,6 +1024,52 @@ __global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ 
   }
 }
 
+// Unpreconditioned form (z = r), used to compare with plain CG:
+// p += alpha w, r -= alpha q, partial ||r||^2.
+template <class S>
+__global__ __launch_bounds__(256) void k_update_plain(Geo g, double* __restrict__ p, const S* __restrict__ w,
+                                                      S* __restrict__ r, const S* __restrict__ q,
+                                                      double* __restrict__ partials, const DevState* __restrict__ st) {
+  if (st->done) return;
+  __shared__ double red[16];
+  const double alpha = st->alpha;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    p[i] += alpha * (double)w[i];
+    const S rs = (S)((double)r[i] - alpha * (double)q[i]);
+    r[i] = rs;
+    acc += (double)rs * (double)rs;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// partial x . x
+template <class S>
+__global__ __launch_bounds__(256) void k_norm2(Geo g, const S* __restrict__ x, double* __restrict__ partials,
+                                               const DevState* __restrict__ st) {
+  if (st && st->done) return;
+  __shared__ double red[16];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride)
+    acc += (double)x[i] * (double)x[i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// w = r + beta w (init: w = r)
+template <class S>
+__global__ __launch_bounds__(256) void k_dir_plain(Geo g, const S* __restrict__ r, S* __restrict__ w,
+                                                   const DevState* __restrict__ st, int init) {
+  if (st->done) return;
+  const double beta = st->beta;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride)
+    w[i] = init ? r[i] : (S)((double)r[i] + beta * (double)w[i]);
+}
+
 // Plain copy (bandwidth calibration of the hardware byte counters).
 __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;

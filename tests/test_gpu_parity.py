@@ -343,3 +343,33 @@ def test_orthotropic_operator_and_solution_match_oracle():
     pref = O.decanonical(O.pcg(pb, rtol=1e-13).p, axis)
     assert np.abs(p - pref).max() < 1e-9 * np.abs(pref).max()
     plan.close()
+
+
+# ------------------------------------------------ preconditioner comparisons
+def test_plain_cg_grows_with_grid_and_dct_pcg_does_not():
+    """prop:cond: cond(A) ~ nL^2, so plain CG needs about twice the passes when
+    the grid doubles; the DCT/Thomas preconditioner keeps the count flat.
+    Both reach the same K_eff (center ball, kappa_inc = 10)."""
+    its_cg, its_pcg = [], []
+    for n in (32, 64, 128):
+        kap = dev(rvegen.center_ball(n, 10.0))
+        a = etc.solve(kap, 2, rtol=1e-8, precond="none", max_iter=20000)
+        b = etc.solve(kap, 2, rtol=1e-8)
+        assert a["status"] == "ok" and b["status"] == "ok"
+        assert abs(a["keff"] - b["keff"]) < 1e-7 * b["keff"]
+        its_cg.append(a["iters"])
+        its_pcg.append(b["iters"])
+    assert its_cg[1] > 1.6 * its_cg[0] and its_cg[2] > 1.6 * its_cg[1], its_cg
+    assert max(its_pcg) - min(its_pcg) <= 6, its_pcg
+
+
+def test_reference_parameter_modes_reach_the_same_keff():
+    """'one' and 'mid' reference parameters change the pass count, not K_eff."""
+    kap = dev(rvegen.center_ball(48, 1000.0))
+    mid = etc.solve(kap, 2, rtol=1e-9)
+    one = etc.solve(kap, 2, rtol=1e-9, kref="one")
+    usr = etc.solve(kap, 2, rtol=1e-9, kref="user", kref_user=[2.0, 2.0, 2.0, 2.0, 2.0])
+    for o in (one, usr):
+        assert o["status"] == "ok"
+        assert abs(o["keff"] - mid["keff"]) < 1e-7 * mid["keff"]
+    assert one["kref"] == [1.0] * 5
