@@ -90,6 +90,7 @@ struct etc_plan {
   DevState* st;
   double* hist;
   double* padj;       // adjoint state (want_grad), else nullptr
+  void* dlt;          // mixed form: float32 solution increment since the last refinement
   DevState* st_host;  // pinned
   DctPlan dpa, dpb;
   LaunchCfg lc;
@@ -145,7 +146,7 @@ DctPlan make_dct_plan(int N) {
 
 struct Sizes {
   size_t off_kap_s, off_kap_hi, off_src, off_faces, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
-      off_part, off_st, off_hist, off_padj, total;
+      off_part, off_st, off_hist, off_padj, off_dlt, total;
   int max_partials;
 };
 
@@ -290,6 +291,7 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
   s.off_st = take(sizeof(DevState));
   s.off_hist = take((size_t)(o.max_iter + 2) * sizeof(double));
   s.off_padj = take(o.want_grad ? V * sizeof(double) : 0);
+  s.off_dlt = take(o.precision == ETC_MIXED ? V * sizeof(float) : 0);
   s.total = off;
   return s;
 }
@@ -453,7 +455,7 @@ template <class S> struct Ops {
     const Geo& g = P->g;
     S* r = (S*)P->r;
     S* w = (S*)P->w;
-    k_init<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, r, kap(P), rhs(P), P->partials);
+    k_init<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, r, kap(P), rhs(P), (S*)P->dlt, P->partials);
     LAUNCHCHK("init");
     etc_status s = fin(P, FIN_BNORM, lc.gridStride);
     if (s) return s;
@@ -484,6 +486,16 @@ template <class S> struct Ops {
     return precond(P, r, w, 0, P->st, 1, FIN_RHO0);
   }
 
+  // The vector the update step accumulates into: p (FP64) or the float32
+  // increment (mixed).
+  static S* xsol(etc_plan* P) { return P->dlt ? (S*)P->dlt : (S*)(void*)P->p; }
+
+  static etc_status flush(etc_plan* P) {
+    k_flush<<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, (float*)P->dlt, P->st);
+    LAUNCHCHK("flush");
+    return ETC_OK;
+  }
+
   // One pass of plain CG (z = r).
   static etc_status iteration_plain(etc_plan* P) {
     const LaunchCfg& lc = P->lc;
@@ -494,10 +506,11 @@ template <class S> struct Ops {
     etc_status s;
     if ((s = apply_A_launch(P, w, q, P->partials, P->st, 1))) return s;
     if ((s = fin(P, FIN_ALPHA, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
-    k_update_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, w, r, q, P->partials, P->st);
+    k_update_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, xsol(P), w, r, q, P->partials, P->st);
     LAUNCHCHK("update");
     if ((s = fin(P, FIN_RR, lc.gridStride))) return s;
     if (P->prec == ETC_MIXED) {
+      if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
       if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
     }
@@ -531,13 +544,15 @@ template <class S> struct Ops {
     // p += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
     timer_begin(P, 2);
     k_rows_fwd<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(g, P->dpb, twb, nullptr, t, lc.rpb,
-                                                                         lc.nrows, P->p, w, r, q, P->partials,
+                                                                         lc.nrows, xsol(P), w, r, q, P->partials,
                                                                          P->st, 1);
     timer_end(P, 2);
     LAUNCHCHK("update_rows_fwd");
     if ((s = fin(P, FIN_RR, lc.gridRows))) return s;
     if (P->prec == ETC_MIXED) {
-      // replace r by the float64 true residual when requested, and redo DCT_b
+      // fold the increment into p, replace r by the float64 true residual
+      // when requested, and redo DCT_b
+      if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
       if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
       k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
@@ -789,6 +804,7 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
   P->st = (DevState*)(b + sz.off_st);
   P->hist = (double*)(b + sz.off_hist);
   P->padj = o.want_grad ? (double*)(b + sz.off_padj) : nullptr;
+  P->dlt = (P->prec == ETC_MIXED) ? (void*)(b + sz.off_dlt) : nullptr;
 
   auto bail = [&](etc_status st) {
     etc_destroy(P);

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __res
 // 2 kappa~ p_out on the last), partial ||b||^2.
 template <class S>
 __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* __restrict__ r, Kap<S> kp, Rhs rh,
-                                              double* __restrict__ partials) {
+                                              S* __restrict__ dlt, double* __restrict__ partials) {
   __shared__ double red[16];
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -204,6 +204,7 @@ __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* 
     const int64_t k = i / g.plane, col = i - k * g.plane;
     const double bv = rhs_at(g, kp, rh, i, k, col);
     p[i] = 0.0;
+    if (dlt) dlt[i] = S(0);
     const S bs = (S)bv;
     r[i] = bs;
     acc += (double)bs * (double)bs;
@@ -338,12 +339,14 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
 constexpr int UNR = 8;
 
 // Rows are the contiguous b lines; a block owns `rpb` whole rows.
-// MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): p += alpha w,
-// r -= alpha q, partial ||r||^2, t = DCT_b(r).
+// MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): x += alpha w,
+// r -= alpha q, partial ||r||^2, t = DCT_b(r).  x is the solution p in the
+// FP64 form and the float32 increment since the last refinement in the
+// mixed form (flushed into the float64 p by k_flush).
 template <class S, class T, int MODE>
 __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
-                                                  double* __restrict__ p, const S* __restrict__ w, S* __restrict__ r,
+                                                  S* __restrict__ p, const S* __restrict__ w, S* __restrict__ r,
                                                   const S* __restrict__ q, double* __restrict__ partials,
                                                   const DevState* __restrict__ st, int gate) {
   if (gated_out(st, gate)) return;
@@ -370,7 +373,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
-          pv[u] = p[base + e];
+          pv[u] = (double)p[base + e];
           wv[u] = (double)w[base + e];
           rv[u] = (double)r[base + e];
           qv[u] = (double)q[base + e];
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
-          p[base + e] = pv[u] + alpha * wv[u];
+          p[base + e] = (S)(pv[u] + alpha * wv[u]);
           const S rs = (S)(rv[u] - alpha * qv[u]);
           r[base + e] = rs;
           acc += (double)rs * (double)rs;
@@ -1027,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ 
 // Unpreconditioned form (z = r), used to compare with plain CG:
 // p += alpha w, r -= alpha q, partial ||r||^2.
 template <class S>
-__global__ __launch_bounds__(256) void k_update_plain(Geo g, double* __restrict__ p, const S* __restrict__ w,
+__global__ __launch_bounds__(256) void k_update_plain(Geo g, S* __restrict__ p, const S* __restrict__ w,
                                                       S* __restrict__ r, const S* __restrict__ q,
                                                       double* __restrict__ partials, const DevState* __restrict__ st) {
   if (st->done) return;
@@ -1036,7 +1039,7 @@ __global__ __launch_bounds__(256) void k_update_plain(Geo g, double* __restrict_
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    p[i] += alpha * (double)w[i];
+    p[i] = (S)((double)p[i] + alpha * (double)w[i]);
     const S rs = (S)((double)r[i] - alpha * (double)q[i]);
     r[i] = rs;
     acc += (double)rs * (double)rs;
@@ -1068,6 +1071,17 @@ __global__ __launch_bounds__(256) void k_dir_plain(Geo g, const S* __restrict__ 
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride)
     w[i] = init ? r[i] : (S)((double)r[i] + beta * (double)w[i]);
+}
+
+// Mixed form, at a refinement: p += increment, increment = 0 (float64 p).
+__global__ __launch_bounds__(256) void k_flush(Geo g, double* __restrict__ p, float* __restrict__ dlt,
+                                               const DevState* __restrict__ st) {
+  if (st->done || !st->refine) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+    p[i] += (double)dlt[i];
+    dlt[i] = 0.0f;
+  }
 }
 
 // Plain copy (bandwidth calibration of the hardware byte counters).
