@@ -223,6 +223,9 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
                                                  double* __restrict__ partials, const DevState* __restrict__ st,
                                                  int gate, int kchunk) {
   if (gated_out(st, gate)) return;
+  // planes loaded per step: KU planes of w and kappa are requested together
+  // so each thread keeps several HBM loads in flight along the k march
+  constexpr int KU = 4;
   __shared__ double red[16];
   const int b = blockIdx.x * 64 + threadIdx.x;
   const int a = blockIdx.y * 4 + threadIdx.y;
@@ -236,6 +239,7 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
   if (valid) {
     const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
     const int64_t col = (int64_t)a * g.nb + b;
+    const bool has_am = a > 0, has_ap = a + 1 < g.na, has_bm = b > 0, has_bp = b + 1 < g.nb;
     int64_t i = (int64_t)k0 * g.plane + col;
     C wc = (C)w[i], kc = (C)ks[i];
     C wm = C(0), km = C(1);
@@ -243,29 +247,46 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
       wm = (C)w[i - g.plane];
       km = (C)ks[i - g.plane];
     }
-    for (int k = k0; k < k1; ++k, i += g.plane) {
-      C wp = C(0), kpp = C(1);
-      if (k + 1 < g.nL) {
-        wp = (C)w[i + g.plane];
-        kpp = (C)ks[i + g.plane];
+    for (int k = k0; k < k1; k += KU) {
+      // next KU planes (plane k+1+u), guarded by the grid
+      C wn[KU], kn[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int kk = k + 1 + u;
+        if (kk < g.nL && kk <= k1) {
+          wn[u] = (C)w[i + (int64_t)(u + 1) * g.plane];
+          kn[u] = (C)ks[i + (int64_t)(u + 1) * g.plane];
+        } else {
+          wn[u] = C(0);
+          kn[u] = C(1);
+        }
       }
-      C qv;
-      if (k > 0) qv = fL * harm(kc, km) * (wc - wm);
-      else qv = C(2) * fL * kc * wc;
-      if (k + 1 < g.nL) qv += fL * harm(kc, kpp) * (wc - wp);
-      else qv += C(2) * fL * kc * wc;
-      const C kac = ORTHO ? (C)ka[i] : kc, kbc = ORTHO ? (C)kb[i] : kc;
-      if (a > 0) qv += fa * harm(kac, (C)ka[i - g.nb]) * (wc - (C)w[i - g.nb]);
-      if (a + 1 < g.na) qv += fa * harm(kac, (C)ka[i + g.nb]) * (wc - (C)w[i + g.nb]);
-      if (b > 0) qv += fb * harm(kbc, (C)kb[i - 1]) * (wc - (C)w[i - 1]);
-      if (b + 1 < g.nb) qv += fb * harm(kbc, (C)kb[i + 1]) * (wc - (C)w[i + 1]);
-      const S qs = (S)qv;
-      q[i] = qs;
-      acc += (double)wc * (double)qs;
-      wm = wc;
-      km = kc;
-      wc = wp;
-      kc = kpp;
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int kk = k + u;
+        if (kk < k1) {
+          const int64_t ii = i + (int64_t)u * g.plane;
+          const C wp = wn[u], kpp = kn[u];
+          C qv;
+          if (kk > 0) qv = fL * harm(kc, km) * (wc - wm);
+          else qv = C(2) * fL * kc * wc;
+          if (kk + 1 < g.nL) qv += fL * harm(kc, kpp) * (wc - wp);
+          else qv += C(2) * fL * kc * wc;
+          const C kac = ORTHO ? (C)ka[ii] : kc, kbc = ORTHO ? (C)kb[ii] : kc;
+          if (has_am) qv += fa * harm(kac, (C)ka[ii - g.nb]) * (wc - (C)w[ii - g.nb]);
+          if (has_ap) qv += fa * harm(kac, (C)ka[ii + g.nb]) * (wc - (C)w[ii + g.nb]);
+          if (has_bm) qv += fb * harm(kbc, (C)kb[ii - 1]) * (wc - (C)w[ii - 1]);
+          if (has_bp) qv += fb * harm(kbc, (C)kb[ii + 1]) * (wc - (C)w[ii + 1]);
+          const S qs = (S)qv;
+          q[ii] = qs;
+          acc += (double)wc * (double)qs;
+          wm = wc;
+          km = kc;
+          wc = wp;
+          kc = kpp;
+        }
+      }
+      i += (int64_t)KU * g.plane;
     }
   }
   if (partials) {
