@@ -155,10 +155,31 @@ etc_status etc_setup_ex(const etc_problem* problem, etc_dtype dt, const int64_t 
 etc_status etc_workspace_size_ex(const etc_problem* problem, const int64_t n[3], etc_dtype dt, int axis,
                                  const etc_options* opt, size_t* bytes);
 
+/* A batch of `nbatch` independent RVEs of one size: `kappa` holds nbatch
+ * user-layout arrays back to back (nbatch x n[0] x n[1] x n[2]), isotropic,
+ * one Dirichlet pair for all.  One plan stacks them along the load axis;
+ * every kernel of a pass covers the whole batch in one launch, and each
+ * instance keeps its own reference medium, PCG scalars, exit test and
+ * convergence flag (an instance that has converged is skipped by every later
+ * kernel of the solve).  etc_solve runs until every instance is done; solution
+ * and gradient buffers are batch-shaped like kappa. */
+etc_status etc_setup_batch(const void* kappa, etc_dtype dt, const int64_t n[3], int nbatch, etc_bc bc, int axis,
+                           const etc_options* opt, etc_plan** plan);
+etc_status etc_workspace_size_batch(const int64_t n[3], int nbatch, etc_dtype dt, int axis, const etc_options* opt,
+                                    size_t* bytes);
+
+/* Per-instance passes, status and last relative residual of the last solve
+ * (host arrays of nbatch entries; any may be NULL). */
+etc_status etc_batch_results(const etc_plan* plan, int* iters, int* status, double* relres);
+
+/* Per-instance K_out and K_in (host arrays of nbatch entries, k_in nullable). */
+etc_status etc_keff_batch(etc_plan* plan, double* k_out, double* k_in);
+
 /* Execution phase: PCG of alg:pcg from p0 (device, user layout, float64;
  * NULL = zero) until ||r|| / ||b|| <= rtol or max_iter passes.  Returns
  * ETC_OK, ETC_NOT_CONVERGED (results still readable) or an error.  `res` may
- * be NULL.  Synchronises the plan's stream. */
+ * be NULL; for a batch it describes instance 0 and the status is the worst
+ * over the batch.  Synchronises the plan's stream. */
 etc_status etc_solve(etc_plan* plan, const double* p0, etc_result* res);
 
 /* Effective conductivity along the load axis after etc_solve (host doubles):

@@ -21,7 +21,7 @@ __all__ = [
     "EtcError", "library_path", "load_library", "etc_workspace_size", "etc_setup", "etc_solve", "etc_keff",
     "etc_get_solution", "etc_residual_history", "etc_apply_A", "etc_apply_Minv", "etc_set_kernel_timer",
     "etc_kernel_time", "etc_copy_f64", "etc_destroy", "etc_last_error", "etc_version", "Plan", "solve",
-    "STATUS", "etc_grad", "keff",
+    "STATUS", "etc_grad", "keff", "etc_setup_batch", "etc_batch_results", "etc_keff_batch", "solve_batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -91,6 +91,15 @@ _SYMBOLS = {
                                     ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]),
     "etc_workspace_size_ex": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
                                              ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]),
+    "etc_setup_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                       _BC, ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_void_p)]),
+    "etc_workspace_size_batch": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, ctypes.POINTER(_Options),
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "etc_batch_results": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "etc_keff_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]),
     "etc_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]),
     "etc_keff": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_double)]),
@@ -203,6 +212,7 @@ class Plan:
         self.stream = stream
         order = [axis] + [d for d in range(3) if d != axis]
         self.canonical_shape = tuple(self.shape[d] for d in order)
+        self.nbatch = 1
 
     @property
     def storage_dtype(self):
@@ -280,6 +290,66 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
                                        int(axis), ctypes.byref(o), ctypes.byref(h)))
     del keep
     return Plan(h, ws, k0.shape, int(axis), precision, k0.device, stream)
+
+
+def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
+                    rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
+                    kref: str = "mid", kref_user=None, L=None, want_grad: bool = False,
+                    precond: str = "dct") -> Plan:
+    """Batch of same-size RVEs: ``kappa`` has shape (B, n0, n1, n2)."""
+    torch = _torch()
+    if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda" or kappa.dim() != 4:
+        raise ValueError("kappa must be a 4D torch tensor (batch, n0, n1, n2) on a GPU device")
+    if kappa.dtype not in (torch.float64, torch.float32):
+        raise ValueError("kappa must be float64 or float32")
+    kappa = kappa.contiguous()
+    dtype = "float64" if kappa.dtype == torch.float64 else "float32"
+    stream = torch.cuda.current_stream(kappa.device)
+    o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
+                 want_grad, precond)
+    nb = int(kappa.shape[0])
+    n = _dims(kappa.shape[1:])
+    nbytes = ctypes.c_size_t(0)
+    _check(load_library().etc_workspace_size_batch(n, nb, _DTYPE[dtype], int(axis), ctypes.byref(o),
+                                                   ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=kappa.device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = int(nbytes.value)
+    h = ctypes.c_void_p(0)
+    _check(load_library().etc_setup_batch(kappa.data_ptr(), _DTYPE[dtype], n, nb, _BC(float(p_in), float(p_out)),
+                                          int(axis), ctypes.byref(o), ctypes.byref(h)))
+    plan = Plan(h, ws, kappa.shape[1:], int(axis), precision, kappa.device, stream)
+    plan.nbatch = nb
+    plan.shape = tuple(kappa.shape)
+    plan.canonical_shape = (nb,) + plan.canonical_shape
+    return plan
+
+
+def etc_batch_results(plan: Plan) -> dict:
+    nb = plan.nbatch
+    it = (ctypes.c_int * nb)()
+    stt = (ctypes.c_int * nb)()
+    rr = (ctypes.c_double * nb)()
+    _check(load_library().etc_batch_results(plan.handle, it, stt, rr))
+    return {"iters": list(it), "status": [STATUS.get(v, v) for v in stt], "relres": list(rr)}
+
+
+def etc_keff_batch(plan: Plan) -> dict:
+    nb = plan.nbatch
+    ko = (ctypes.c_double * nb)()
+    ki = (ctypes.c_double * nb)()
+    _check(load_library().etc_keff_batch(plan.handle, ko, ki))
+    return {"keff": list(ko), "k_in": list(ki)}
+
+
+def solve_batch(kappa, axis: int = 0, **kw) -> dict:
+    """Setup + solve + per-instance K_eff for a (B, n0, n1, n2) batch."""
+    plan = etc_setup_batch(kappa, axis, **kw)
+    out = etc_solve(plan)
+    out.update(etc_batch_results(plan))
+    out.update(etc_keff_batch(plan))
+    plan.close()
+    return out
 
 
 def etc_solve(plan: Plan, p0=None) -> dict:

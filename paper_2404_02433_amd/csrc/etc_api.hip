@@ -42,12 +42,16 @@ constexpr int kThomasTB = 16;          // modes (lines) per tridiagonal block
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Launch shapes.  Every grid carries the instance index of a batch in its
+// last dimension; nX is the number of blocks (= partial sums) per instance.
 struct LaunchCfg {
   // operator / residual: block (64, 4), k chunk
   dim3 gridA;
-  int kchunk;
+  int kchunk, nA;
   // rows
-  int rpb, nrows, gridRows;
+  int rpb, nrows;
+  dim3 gridRows;
+  int nRows;
   size_t ldsRows;
   // columns
   int tb;
@@ -55,10 +59,12 @@ struct LaunchCfg {
   size_t ldsCols;
   // tridiagonal
   dim3 gridThomas;
-  int Puse, maxm;
+  int Puse, maxm, nThomas;
   // grid-stride kernels
-  int gridStride;
-  int gridKeff;
+  dim3 gridStride;
+  int nStride;
+  dim3 gridKeff;
+  int nKeff;
 };
 
 }  // namespace
@@ -91,15 +97,17 @@ struct etc_plan {
   double* hist;
   double* padj;       // adjoint state (want_grad), else nullptr
   void* dlt;          // mixed form: float32 solution increment since the last refinement
-  DevState* st_host;  // pinned
+  DevState* st_host;  // pinned, one per instance
   DctPlan dpa, dpb;
   LaunchCfg lc;
-  double kref[5];
-  double ext[10];
-  double lam_lo, lam_hi;
+  int nseg;                    // instances in the batch (1 for a single RVE)
+  int hstride;                 // residual-history entries per instance
+  std::vector<double> kref;    // 5 per instance (load-axis, a, b, in, out)
+  double* kref_d;              // device copy
+  std::vector<double> lam_lo, lam_hi;
   bool solved;
-  int last_iters;
-  int last_status;
+  int last_iters;              // max over instances
+  int last_status;             // worst over instances
   // kernel timer
   int timer_id;
   std::vector<hipEvent_t> ev;
@@ -146,7 +154,7 @@ DctPlan make_dct_plan(int N) {
 
 struct Sizes {
   size_t off_kap_s, off_kap_hi, off_src, off_faces, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
-      off_part, off_st, off_hist, off_padj, off_dlt, total;
+      off_kref, off_part, off_st, off_hist, off_padj, off_dlt, total;
   int max_partials;
 };
 
@@ -162,13 +170,16 @@ void canonical_dims(const int64_t n[3], int axis, int& nL, int& na, int& nb) {
 LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt) {
   LaunchCfg lc{};
   const size_t cx_sz = 2 * elt;
-  // operator: aim for >= ~4096 blocks
+  const int ns = g.nseg;
+  // operator: aim for >= ~4096 blocks over the whole batch
   const int gx = (g.nb + 63) / 64, gy = (g.na + 3) / 4;
-  const int64_t cols = (int64_t)gx * gy;
+  const int64_t cols = (int64_t)gx * gy * ns;
   int kchunk = g.nL;
   while (kchunk > 8 && cols * ((g.nL + kchunk - 1) / kchunk) < 4096) kchunk = (kchunk + 1) / 2;
+  const int nch = (g.nL + kchunk - 1) / kchunk;
   lc.kchunk = kchunk;
-  lc.gridA = dim3(gx, gy, (g.nL + kchunk - 1) / kchunk);
+  lc.gridA = dim3(gx, gy, nch * ns);
+  lc.nA = gx * gy * nch;
   // rows (b axis)
   {
     const size_t line_bytes = (size_t)dpb.lstride * cx_sz;
@@ -178,7 +189,8 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     lc.nrows = g.nL * g.na;
     rpb = std::min(rpb, lc.nrows);
     lc.rpb = rpb;
-    lc.gridRows = (lc.nrows + rpb - 1) / rpb;
+    lc.nRows = (lc.nrows + rpb - 1) / rpb;
+    lc.gridRows = dim3(lc.nRows, ns);
     lc.ldsRows = (size_t)rpb * line_bytes;
   }
   // columns (a axis)
@@ -191,7 +203,7 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     else if (tb >= 8) tb = 8;
     tb = std::min(tb, g.nb);
     lc.tb = tb;
-    lc.gridCols = dim3((g.nb + tb - 1) / tb, g.nL, 1);
+    lc.gridCols = dim3((g.nb + tb - 1) / tb, g.nL * ns, 1);
     lc.ldsCols = (size_t)tb * line_bytes;
   }
   // tridiagonal
@@ -200,22 +212,26 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     int m = (g.nL + Puse - 1) / Puse;
     lc.Puse = Puse;
     lc.maxm = m;
-    lc.gridThomas = dim3((g.nb + kThomasTB - 1) / kThomasTB, g.na, 1);
+    lc.gridThomas = dim3((g.nb + kThomasTB - 1) / kThomasTB, g.na, ns);
+    lc.nThomas = lc.gridThomas.x * lc.gridThomas.y;
   }
   int64_t gs = (g.V + kThreads - 1) / kThreads;
-  lc.gridStride = (int)std::min<int64_t>(gs, kMaxGridStride);
+  lc.nStride = (int)std::min<int64_t>(gs, std::max<int64_t>(8, kMaxGridStride / ns));
+  lc.gridStride = dim3(lc.nStride, ns);
   int64_t gk = (g.plane + kThreads - 1) / kThreads;
-  lc.gridKeff = (int)std::min<int64_t>(gk, 1024);
+  lc.nKeff = (int)std::min<int64_t>(gk, 1024);
+  lc.gridKeff = dim3(lc.nKeff, ns);
   return lc;
 }
 
+// Largest number of partial sums any kernel writes per instance.
 int max_partials_of(const LaunchCfg& lc) {
   int64_t m = 1024;
-  m = std::max<int64_t>(m, (int64_t)lc.gridA.x * lc.gridA.y * lc.gridA.z);
-  m = std::max<int64_t>(m, lc.gridRows);
-  m = std::max<int64_t>(m, (int64_t)lc.gridThomas.x * lc.gridThomas.y);
-  m = std::max<int64_t>(m, (int64_t)lc.gridStride * 12);
-  m = std::max<int64_t>(m, (int64_t)lc.gridKeff * 2);
+  m = std::max<int64_t>(m, lc.nA);
+  m = std::max<int64_t>(m, lc.nRows);
+  m = std::max<int64_t>(m, lc.nThomas);
+  m = std::max<int64_t>(m, (int64_t)lc.nStride * 12);
+  m = std::max<int64_t>(m, (int64_t)lc.nKeff * 2);
   return (int)m;
 }
 
@@ -252,7 +268,8 @@ struct ProblemShape {
   bool ortho, src, faces;
 };
 
-Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& o, ProblemShape ps = {false, false, false}) {
+// Geometry of one instance (nseg instances of it in a batch).
+Geo make_geo(const int64_t n[3], int axis, int nseg) {
   int nL, na, nb;
   canonical_dims(n, axis, nL, na, nb);
   Geo g{};
@@ -261,6 +278,13 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
   g.nb = nb;
   g.plane = (int64_t)na * nb;
   g.V = g.plane * nL;
+  g.nseg = nseg;
+  return g;
+}
+
+Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& o, ProblemShape ps, int nseg) {
+  const Geo g = make_geo(n, axis, nseg);
+  const int na = g.na, nb = g.nb;
   const size_t es = elt_size(o.precision);
   DctPlan dpa = make_dct_plan(na), dpb = make_dct_plan(nb);
   LaunchCfg lc = make_launch(g, dpa, dpb, es);
@@ -271,7 +295,7 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
     off += align_up(bytes);
     return o2;
   };
-  const size_t V = (size_t)g.V;
+  const size_t V = (size_t)g.V * nseg;  // every volume array holds the whole batch
   const int ncomp = ps.ortho ? 3 : 1;
   s.off_kap_s = take(ncomp * V * es);
   s.off_kap_hi = take((o.precision == ETC_MIXED && dt == ETC_F64) ? ncomp * V * sizeof(double) : 0);
@@ -286,10 +310,11 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
   s.off_lam_b = take(nb * sizeof(double));
   s.off_tw_a = take((size_t)4 * na * 2 * es);
   s.off_tw_b = take((size_t)4 * nb * 2 * es);
+  s.off_kref = take((size_t)5 * nseg * sizeof(double));
   s.max_partials = max_partials_of(lc);
-  s.off_part = take((size_t)s.max_partials * sizeof(double));
-  s.off_st = take(sizeof(DevState));
-  s.off_hist = take((size_t)(o.max_iter + 2) * sizeof(double));
+  s.off_part = take((size_t)s.max_partials * nseg * sizeof(double));
+  s.off_st = take(sizeof(DevState) * nseg);
+  s.off_hist = take((size_t)(o.max_iter + 2) * nseg * sizeof(double));
   s.off_padj = take(o.want_grad ? V * sizeof(double) : 0);
   s.off_dlt = take(o.precision == ETC_MIXED ? V * sizeof(float) : 0);
   s.total = off;
@@ -332,32 +357,48 @@ template <class S> struct Ops {
 
   static Rhs rhs(const etc_plan* P) { return Rhs{P->src, P->pin_face, P->pout_face}; }
 
-  // canonical copy of one user-layout array (dtype In) into dst / dst_hi
+  // canonical copy of one instance of a user-layout array (dtype In)
   template <class In, class Out>
   static etc_status canon_one(etc_plan* P, const In* src, Out* dst, double* dst_hi) {
-    const Geo& g = P->g;
+    Geo g = P->g;
+    g.nseg = 1;
     if (P->axis == 2) {
       dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
       k_canon_axis2<In, Out><<<grid, dim3(32, 8), 0, P->stream>>>(src, dst, dst_hi, g);
     } else {
-      k_canon_rows<In, Out><<<P->lc.gridStride, kThreads, 0, P->stream>>>(src, dst, dst_hi, P->axis, g);
+      k_canon_rows<In, Out><<<P->lc.nStride, kThreads, 0, P->stream>>>(src, dst, dst_hi, P->axis, g);
     }
     LAUNCHCHK("canon");
     return ETC_OK;
   }
 
-  static etc_status canon(etc_plan* P, const void* const comp_user[3], const double* source) {
+  // Canonical copies of instance `inst` (conductivity components, source)
+  // and its family extrema into the first 12 * nStride partials.
+  static etc_status canon(etc_plan* P, const void* const comp_user[3], const double* source, int inst) {
+    const int64_t off = (int64_t)inst * P->g.V;
+    const size_t in_es = (P->in_dt == ETC_F64) ? sizeof(double) : sizeof(float);
     for (int c = 0; c < (P->ortho ? 3 : 1); ++c) {
-      etc_status s = (P->in_dt == ETC_F64)
-                         ? canon_one<double, S>(P, (const double*)comp_user[c], (S*)P->kap_s[c], P->kap_hi[c])
-                         : canon_one<float, S>(P, (const float*)comp_user[c], (S*)P->kap_s[c], P->kap_hi[c]);
+      const char* src = (const char*)comp_user[c] + (size_t)off * in_es;
+      S* dst = (S*)P->kap_s[c] + off;
+      double* dhi = P->kap_hi[c] ? P->kap_hi[c] + off : nullptr;
+      etc_status s = (P->in_dt == ETC_F64) ? canon_one<double, S>(P, (const double*)src, dst, dhi)
+                                           : canon_one<float, S>(P, (const float*)src, dst, dhi);
       if (s) return s;
     }
     if (source) {
-      etc_status s = canon_one<double, double>(P, source, P->src, nullptr);
+      etc_status s = canon_one<double, double>(P, source + off, P->src + off, nullptr);
       if (s) return s;
     }
-    k_extrema<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, kap(P), P->partials);
+    Kap<S> k = kap(P);
+    k.L += off;
+    k.A += off;
+    k.B += off;
+    if (k.hL) k.hL += off;
+    if (k.hA) k.hA += off;
+    if (k.hB) k.hB += off;
+    Geo g = P->g;
+    g.nseg = 1;
+    k_extrema<S><<<P->lc.nStride, kThreads, 0, P->stream>>>(g, k, P->partials);
     LAUNCHCHK("extrema");
     return ETC_OK;
   }
@@ -380,11 +421,7 @@ template <class S> struct Ops {
 
   static RefMedium ref(const etc_plan* P) {
     RefMedium rm;
-    rm.kL = P->kref[0];
-    rm.ka = P->kref[1];
-    rm.kb = P->kref[2];
-    rm.kin = P->kref[3];
-    rm.kout = P->kref[4];
+    rm.kref = P->kref_d;
     rm.lam_a = P->lam_a;
     rm.lam_b = P->lam_b;
     return rm;
@@ -404,8 +441,10 @@ template <class S> struct Ops {
     return ETC_OK;
   }
 
-  static etc_status fin(etc_plan* P, int op, int n) {
-    k_fin<<<1, 1024, 0, P->stream>>>(op, P->partials, n, P->st, P->hist);
+  // finalize over every instance: n partials each, `pstride` apart
+  static etc_status fin(etc_plan* P, int op, int n, int64_t pstride, const double* partials = nullptr) {
+    k_fin<<<P->nseg, 1024, 0, P->stream>>>(op, partials ? partials : P->partials, n, pstride, P->st, P->hist,
+                                           P->hstride);
     LAUNCHCHK("finalize");
     return ETC_OK;
   }
@@ -435,7 +474,7 @@ template <class S> struct Ops {
     LAUNCHCHK("cols_fwd");
     etc_status s = thomas(P, t, P->partials, st, gate);
     if (s) return s;
-    s = fin(P, fin_op, lc.gridThomas.x * lc.gridThomas.y);
+    s = fin(P, fin_op, lc.nThomas, lc.nThomas);
     if (s) return s;
     k_cols<S, T, +1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
     LAUNCHCHK("cols_inv");
@@ -457,28 +496,23 @@ template <class S> struct Ops {
     S* w = (S*)P->w;
     k_init<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, P->p, r, kap(P), rhs(P), (S*)P->dlt, P->partials);
     LAUNCHCHK("init");
-    etc_status s = fin(P, FIN_BNORM, lc.gridStride);
+    etc_status s = fin(P, FIN_BNORM, lc.nStride, lc.nStride);
     if (s) return s;
     if (p0_user) {
       // canonical copy of p0 into p (double), then r = b - A p0
-      if (P->axis == 2) {
-        dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
-        k_canon_axis2<double, double><<<grid, dim3(32, 8), 0, P->stream>>>(p0_user, P->p, nullptr, g);
-      } else {
-        k_canon_rows<double, double><<<lc.gridStride, kThreads, 0, P->stream>>>(p0_user, P->p, nullptr, P->axis, g);
+      for (int inst = 0; inst < P->nseg; ++inst) {
+        s = canon_one<double, double>(P, p0_user + (int64_t)inst * g.V, P->p + (int64_t)inst * g.V, nullptr);
+        if (s) return s;
       }
-      LAUNCHCHK("p0");
       s = residual(P, r, nullptr, 0);
       if (s) return s;
-      LAUNCHCHK("residual");
       // relative residual of the warm start
-      k_fin<<<1, 1024, 0, P->stream>>>(FIN_RR0, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
-      LAUNCHCHK("fin");
+      if ((s = fin(P, FIN_RR0, lc.nA, lc.nA))) return s;
     }
     if (P->opt.precond == ETC_PC_NONE) {
       k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
       LAUNCHCHK("norm2");
-      if ((s = fin(P, FIN_RHO0, lc.gridStride))) return s;
+      if ((s = fin(P, FIN_RHO0, lc.nStride, lc.nStride))) return s;
       k_dir_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, w, P->st, 1);
       LAUNCHCHK("dir");
       return ETC_OK;
@@ -505,18 +539,18 @@ template <class S> struct Ops {
     S* q = (S*)P->q;
     etc_status s;
     if ((s = apply_A_launch(P, w, q, P->partials, P->st, 1))) return s;
-    if ((s = fin(P, FIN_ALPHA, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+    if ((s = fin(P, FIN_ALPHA, lc.nA, lc.nA))) return s;
     k_update_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, xsol(P), w, r, q, P->partials, P->st);
     LAUNCHCHK("update");
-    if ((s = fin(P, FIN_RR, lc.gridStride))) return s;
+    if ((s = fin(P, FIN_RR, lc.nStride, lc.nStride))) return s;
     if (P->prec == ETC_MIXED) {
       if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
-      if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+      if ((s = fin(P, FIN_REFINE, lc.nA, lc.nA))) return s;
     }
     k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
     LAUNCHCHK("norm2");
-    if ((s = fin(P, FIN_BETA, lc.gridStride))) return s;
+    if ((s = fin(P, FIN_BETA, lc.nStride, lc.nStride))) return s;
     k_dir_plain<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, w, P->st, 0);
     LAUNCHCHK("dir");
     return ETC_OK;
@@ -534,27 +568,26 @@ template <class S> struct Ops {
     const cx<T>* twa = (const cx<T>*)P->tw_a;
     const cx<T>* twb = (const cx<T>*)P->tw_b;
     etc_status s;
-    (void)g;
     // q = A w, alpha = rho / (w . q)
     timer_begin(P, 1);
     s = apply_A_launch(P, w, q, P->partials, P->st, 1);
     timer_end(P, 1);
     if (s) return s;
-    if ((s = fin(P, FIN_ALPHA, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
-    // p += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
+    if ((s = fin(P, FIN_ALPHA, lc.nA, lc.nA))) return s;
+    // x += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
     timer_begin(P, 2);
     k_rows_fwd<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(g, P->dpb, twb, nullptr, t, lc.rpb,
                                                                          lc.nrows, xsol(P), w, r, q, P->partials,
                                                                          P->st, 1);
     timer_end(P, 2);
     LAUNCHCHK("update_rows_fwd");
-    if ((s = fin(P, FIN_RR, lc.gridRows))) return s;
+    if ((s = fin(P, FIN_RR, lc.nRows, lc.nRows))) return s;
     if (P->prec == ETC_MIXED) {
       // fold the increment into p, replace r by the float64 true residual
       // when requested, and redo DCT_b
       if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
-      if ((s = fin(P, FIN_REFINE, lc.gridA.x * lc.gridA.y * lc.gridA.z))) return s;
+      if ((s = fin(P, FIN_REFINE, lc.nA, lc.nA))) return s;
       k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
           g, P->dpb, twb, r, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
       LAUNCHCHK("rows_fwd_refine");
@@ -567,7 +600,7 @@ template <class S> struct Ops {
     s = thomas(P, t, P->partials, P->st, 1);
     timer_end(P, 4);
     if (s) return s;
-    if ((s = fin(P, FIN_BETA, lc.gridThomas.x * lc.gridThomas.y))) return s;
+    if ((s = fin(P, FIN_BETA, lc.nThomas, lc.nThomas))) return s;
     timer_begin(P, 5);
     k_cols<S, T, +1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
     timer_end(P, 5);
@@ -585,14 +618,13 @@ template <class S> struct Ops {
     const LaunchCfg& lc = P->lc;
     k_keff<S><<<lc.gridKeff, kThreads, 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), P->partials);
     LAUNCHCHK("keff");
-    k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC0, P->partials, lc.gridKeff, P->st, P->hist);
-    k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC1, P->partials + lc.gridKeff, lc.gridKeff, P->st, P->hist);
-    LAUNCHCHK("fin");
+    etc_status s;
+    if ((s = fin(P, FIN_ACC0, lc.nKeff, 2 * lc.nKeff))) return s;
+    if ((s = fin(P, FIN_ACC1, lc.nKeff, 2 * lc.nKeff, P->partials + lc.nKeff))) return s;
     if (energy) {
       k_energy<S><<<lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), P->partials);
       LAUNCHCHK("energy");
-      k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC2, P->partials, lc.gridStride, P->st, P->hist);
-      LAUNCHCHK("fin");
+      if ((s = fin(P, FIN_ACC2, lc.nStride, lc.nStride))) return s;
     }
     return ETC_OK;
   }
@@ -629,10 +661,7 @@ template <class S> struct Ops {
     const LaunchCfg& lc = P->lc;
     etc_status s = apply_A_launch(P, (const S*)x, (S*)y, dot ? P->partials : nullptr, nullptr, 0);
     if (s) return s;
-    if (dot) {
-      k_fin<<<1, 1024, 0, P->stream>>>(FIN_ACC3, P->partials, lc.gridA.x * lc.gridA.y * lc.gridA.z, P->st, P->hist);
-      LAUNCHCHK("fin");
-    }
+    if (dot) return fin(P, FIN_ACC3, lc.nA, lc.nA);
     return ETC_OK;
   }
 };
@@ -679,7 +708,7 @@ etc_status etc_workspace_size_ex(const etc_problem* pr, const int64_t n[3], etc_
   if (!bytes) return fail(ETC_E_INVALID, "bytes is NULL");
   etc_status s = validate(n, axis, o);
   if (s) return s;
-  *bytes = plan_sizes(n, axis, dt, o, shape_of(pr)).total;
+  *bytes = plan_sizes(n, axis, dt, o, shape_of(pr), 1).total;
   return ETC_OK;
 }
 
@@ -687,16 +716,23 @@ etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const 
   return etc_workspace_size_ex(nullptr, n, dt, axis, opt, bytes);
 }
 
-etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
-                     const etc_options* opt, etc_plan** out) {
-  etc_problem pr;
-  std::memset(&pr, 0, sizeof(pr));
-  pr.kappa[0] = kappa;
-  return etc_setup_ex(&pr, dt, n, bc, axis, opt, out);
+etc_status etc_workspace_size_batch(const int64_t n[3], int nbatch, etc_dtype dt, int axis, const etc_options* opt,
+                                    size_t* bytes) {
+  etc_options o;
+  if (opt) o = *opt;
+  else etc_options_default(&o);
+  if (!bytes) return fail(ETC_E_INVALID, "bytes is NULL");
+  if (nbatch < 1 || nbatch > 4096) return fail(ETC_E_INVALID, "nbatch must be in 1..4096");
+  etc_status s = validate(n, axis, o);
+  if (s) return s;
+  *bytes = plan_sizes(n, axis, dt, o, ProblemShape{false, false, false}, nbatch).total;
+  return ETC_OK;
 }
 
-etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
-                        const etc_options* opt, etc_plan** out) {
+}  // extern "C"
+
+static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t n[3], int nseg, etc_bc bc, int axis,
+                             const etc_options* opt, etc_plan** out) {
   if (!out) return fail(ETC_E_INVALID, "plan is NULL");
   *out = nullptr;
   if (!pr) return fail(ETC_E_INVALID, "problem is NULL");
@@ -716,6 +752,10 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
   if (!(bc.p_in != bc.p_out) || !std::isfinite(bc.p_in) || !std::isfinite(bc.p_out))
     return fail(ETC_E_INVALID, "p_in and p_out must be finite and differ");
   if (o.poll_every < 1) o.poll_every = 1;
+  if (o.want_grad && (ps.ortho || ps.src || ps.faces))
+    return fail(ETC_E_UNSUPPORTED, "etc_grad covers isotropic kappa with constant Dirichlet data only");
+  if (nseg > 1 && (ps.ortho || ps.src || ps.faces))
+    return fail(ETC_E_UNSUPPORTED, "batches take isotropic kappa with constant Dirichlet data");
 
   etc_plan* P = new etc_plan();
   P->opt = o;
@@ -725,15 +765,12 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
   P->stream = (hipStream_t)o.stream;
   P->timer_id = 0;
   P->ev_used = 0;
+  P->nseg = nseg;
+  P->hstride = o.max_iter + 2;
   for (int d = 0; d < 3; ++d) P->n_user[d] = n[d];
-  int nL, na, nb;
-  canonical_dims(n, axis, nL, na, nb);
+  P->g = make_geo(n, axis, nseg);
   Geo& g = P->g;
-  g.nL = nL;
-  g.na = na;
-  g.nb = nb;
-  g.plane = (int64_t)na * nb;
-  g.V = g.plane * nL;
+  const int na = g.na, nb = g.nb;
   {
     double h_user[3] = {1.0, 1.0, 1.0};
     if (o.L[0] > 0.0)
@@ -751,10 +788,12 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
   P->dpa = make_dct_plan(na);
   P->dpb = make_dct_plan(nb);
   P->lc = make_launch(g, P->dpa, P->dpb, es);
+  if (P->lc.gridCols.y > 65535 || P->lc.gridA.z > 65535) {
+    delete P;
+    return fail(ETC_E_UNSUPPORTED, "batch too large: load planes times instances exceeds 65535");
+  }
 
-  if (o.want_grad && (ps.ortho || ps.src || ps.faces))
-    return fail(ETC_E_UNSUPPORTED, "etc_grad covers isotropic kappa with constant Dirichlet data only");
-  Sizes sz = plan_sizes(n, axis, dt, o, ps);
+  Sizes sz = plan_sizes(n, axis, dt, o, ps, nseg);
   P->max_partials = sz.max_partials;
   if (o.workspace) {
     if (o.workspace_bytes < sz.total) {
@@ -772,7 +811,7 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
     }
     P->ws_bytes = sz.total;
   }
-  if (hipHostMalloc((void**)&P->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&P->st_host, sizeof(DevState) * nseg, hipHostMallocDefault) != hipSuccess) {
     if (P->own_ws) (void)hipFree(P->ws);
     delete P;
     return fail(ETC_E_NOMEM, "pinned host allocation failed");
@@ -780,12 +819,12 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
   char* b = P->ws;
   P->ortho = ps.ortho;
   {
-    const size_t vbytes = (size_t)g.V * es;
+    const size_t vbytes = (size_t)g.V * nseg * es;
     const bool hi = (P->prec == ETC_MIXED && dt == ETC_F64);
     for (int c = 0; c < 3; ++c) {
       const int cc = ps.ortho ? c : 0;
       P->kap_s[c] = b + sz.off_kap_s + cc * vbytes;
-      P->kap_hi[c] = hi ? (double*)(b + sz.off_kap_hi) + (size_t)cc * g.V : nullptr;
+      P->kap_hi[c] = hi ? (double*)(b + sz.off_kap_hi) + (size_t)cc * g.V * nseg : nullptr;
     }
   }
   P->src = ps.src ? (double*)(b + sz.off_src) : nullptr;
@@ -800,6 +839,7 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
   P->lam_b = (double*)(b + sz.off_lam_b);
   P->tw_a = b + sz.off_tw_a;
   P->tw_b = b + sz.off_tw_b;
+  P->kref_d = (double*)(b + sz.off_kref);
   P->partials = (double*)(b + sz.off_part);
   P->st = (DevState*)(b + sz.off_st);
   P->hist = (double*)(b + sz.off_hist);
@@ -811,20 +851,7 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
     return st;
   };
 
-  // canonical copy + extrema
   s = (P->prec == ETC_MIXED) ? Ops<float>::lds_limits(P) : Ops<double>::lds_limits(P);
-  if (s) return bail(s);
-  {
-    // user component order -> canonical (load axis, a, b)
-    const void* comp[3] = {pr->kappa[0], pr->kappa[0], pr->kappa[0]};
-    if (ps.ortho) {
-      int order[3] = {axis, 0, 0}, c = 1;
-      for (int d = 0; d < 3; ++d)
-        if (d != axis) order[c++] = d;
-      for (int d = 0; d < 3; ++d) comp[d] = pr->kappa[order[d]];
-    }
-    s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source) : Ops<double>::canon(P, comp, pr->source);
-  }
   if (s) return bail(s);
   if (ps.faces) {
     // face data: [a][b] over the transverse axes in user order (constant pair where NULL)
@@ -840,44 +867,57 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
         hipStreamSynchronize(P->stream) != hipSuccess)
       return bail(fail(ETC_E_HIP, "copying the Dirichlet face data failed"));
   }
-  if (s) return bail(s);
-  std::vector<double> part((size_t)P->lc.gridStride * 12);
-  if (hipMemcpyAsync(part.data(), P->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(P->stream) != hipSuccess)
-    return bail(fail(ETC_E_HIP, "reading the extrema failed"));
-  double mn[5], mx[5], bad = 0.0;
-  for (int f = 0; f < 5; ++f) {
-    mn[f] = INFINITY;
-    mx[f] = -INFINITY;
-  }
-  for (int blk = 0; blk < P->lc.gridStride; ++blk) {
-    for (int f = 0; f < 5; ++f) {
-      mn[f] = std::fmin(mn[f], part[(size_t)blk * 12 + 2 * f]);
-      mx[f] = std::fmax(mx[f], part[(size_t)blk * 12 + 2 * f + 1]);
-    }
-    bad += part[(size_t)blk * 12 + 10];
-  }
-  if (bad > 0.0) return bail(fail(ETC_E_INVALID, "kappa holds values that are <= 0, NaN or Inf"));
-  for (int f = 0; f < 5; ++f) {
-    P->ext[2 * f] = mn[f];
-    P->ext[2 * f + 1] = mx[f];
-  }
-  for (int f = 0; f < 5; ++f) {
-    const bool empty = !(mn[f] <= mx[f]);
-    if (o.kref_mode == ETC_KREF_USER) P->kref[f] = o.kref_user[f];
-    else if (o.kref_mode == ETC_KREF_ONE || empty) P->kref[f] = 1.0;
-    else P->kref[f] = std::sqrt(mn[f] * mx[f]);
-  }
+  // canonical copies, extrema and reference parameters, instance by instance
+  P->kref.assign((size_t)5 * nseg, 1.0);
+  P->lam_lo.assign(nseg, 1.0);
+  P->lam_hi.assign(nseg, 1.0);
   {
-    double lo = INFINITY, hi = -INFINITY;
-    for (int f = 0; f < 5; ++f) {
-      if (!(mn[f] <= mx[f])) continue;
-      lo = std::fmin(lo, mn[f] / P->kref[f]);
-      hi = std::fmax(hi, mx[f] / P->kref[f]);
+    // user component order -> canonical (load axis, a, b)
+    const void* comp[3] = {pr->kappa[0], pr->kappa[0], pr->kappa[0]};
+    if (ps.ortho) {
+      int order[3] = {axis, 0, 0}, c = 1;
+      for (int d = 0; d < 3; ++d)
+        if (d != axis) order[c++] = d;
+      for (int d = 0; d < 3; ++d) comp[d] = pr->kappa[order[d]];
     }
-    P->lam_lo = lo;
-    P->lam_hi = hi;
+    std::vector<double> part((size_t)P->lc.nStride * 12);
+    for (int inst = 0; inst < nseg; ++inst) {
+      s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source, inst)
+                                 : Ops<double>::canon(P, comp, pr->source, inst);
+      if (s) return bail(s);
+      if (hipMemcpyAsync(part.data(), P->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         P->stream) != hipSuccess ||
+          hipStreamSynchronize(P->stream) != hipSuccess)
+        return bail(fail(ETC_E_HIP, "reading the extrema failed"));
+      double mn[5], mx[5], bad = 0.0;
+      for (int f = 0; f < 5; ++f) {
+        mn[f] = INFINITY;
+        mx[f] = -INFINITY;
+      }
+      for (int blk = 0; blk < P->lc.nStride; ++blk) {
+        for (int f = 0; f < 5; ++f) {
+          mn[f] = std::fmin(mn[f], part[(size_t)blk * 12 + 2 * f]);
+          mx[f] = std::fmax(mx[f], part[(size_t)blk * 12 + 2 * f + 1]);
+        }
+        bad += part[(size_t)blk * 12 + 10];
+      }
+      if (bad > 0.0) return bail(fail(ETC_E_INVALID, "kappa holds values that are <= 0, NaN or Inf"));
+      double* kr = &P->kref[(size_t)5 * inst];
+      for (int f = 0; f < 5; ++f) {
+        const bool empty = !(mn[f] <= mx[f]);
+        if (o.kref_mode == ETC_KREF_USER) kr[f] = o.kref_user[f];
+        else if (o.kref_mode == ETC_KREF_ONE || empty) kr[f] = 1.0;
+        else kr[f] = std::sqrt(mn[f] * mx[f]);
+      }
+      double lo = INFINITY, hi = -INFINITY;
+      for (int f = 0; f < 5; ++f) {
+        if (!(mn[f] <= mx[f])) continue;
+        lo = std::fmin(lo, mn[f] / kr[f]);
+        hi = std::fmax(hi, mx[f] / kr[f]);
+      }
+      P->lam_lo[inst] = lo;
+      P->lam_hi[inst] = hi;
+    }
   }
   // tables
   {
@@ -902,6 +942,8 @@ etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3],
         hipMemcpyAsync(P->lam_b, lb.data(), nb * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
         hipMemcpyAsync(P->tw_a, twa.data(), twa.size(), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
         hipMemcpyAsync(P->tw_b, twb.data(), twb.size(), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->kref_d, P->kref.data(), P->kref.size() * sizeof(double), hipMemcpyHostToDevice,
+                       P->stream) != hipSuccess ||
         hipStreamSynchronize(P->stream) != hipSuccess)
       return bail(fail(ETC_E_HIP, "uploading the tables failed"));
   }
@@ -916,9 +958,39 @@ static etc_status reset_state(etc_plan* P) {
   h.max_iter = P->opt.max_iter;
   h.refine_every = (P->prec == ETC_MIXED) ? std::max(0, P->opt.refine_every) : 0;
   h.mixed = (P->prec == ETC_MIXED) ? 1 : 0;
-  *P->st_host = h;
-  HIPCHK(hipMemcpyAsync(P->st, P->st_host, sizeof(DevState), hipMemcpyHostToDevice, P->stream));
+  for (int i = 0; i < P->nseg; ++i) P->st_host[i] = h;
+  HIPCHK(hipMemcpyAsync(P->st, P->st_host, sizeof(DevState) * P->nseg, hipMemcpyHostToDevice, P->stream));
   return ETC_OK;
+}
+
+static etc_status pull_state(etc_plan* P) {
+  HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState) * P->nseg, hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return ETC_OK;
+}
+
+extern "C" {
+
+etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                     const etc_options* opt, etc_plan** out) {
+  etc_problem pr;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.kappa[0] = kappa;
+  return setup_impl(&pr, dt, n, 1, bc, axis, opt, out);
+}
+
+etc_status etc_setup_ex(const etc_problem* pr, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                        const etc_options* opt, etc_plan** out) {
+  return setup_impl(pr, dt, n, 1, bc, axis, opt, out);
+}
+
+etc_status etc_setup_batch(const void* kappa, etc_dtype dt, const int64_t n[3], int nbatch, etc_bc bc, int axis,
+                           const etc_options* opt, etc_plan** out) {
+  if (nbatch < 1 || nbatch > 4096) return fail(ETC_E_INVALID, "nbatch must be in 1..4096");
+  etc_problem pr;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.kappa[0] = kappa;
+  return setup_impl(&pr, dt, n, nbatch, bc, axis, opt, out);
 }
 
 etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
@@ -940,18 +1012,26 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
   int enq = 0;
   const int chunk = P->opt.poll_every;
   for (;;) {
-    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
-    HIPCHK(hipStreamSynchronize(P->stream));
-    if (P->st_host->done || enq > P->opt.max_iter) break;
+    if ((s = pull_state(P))) return s;
+    bool all_done = true;
+    for (int i = 0; i < P->nseg; ++i) all_done = all_done && P->st_host[i].done;
+    if (all_done || enq > P->opt.max_iter) break;
     for (int i = 0; i < chunk; ++i) {
       s = (P->prec == ETC_MIXED) ? Ops<float>::iteration(P) : Ops<double>::iteration(P);
       if (s) return s;
     }
     enq += chunk;
   }
-  const DevState& h = *P->st_host;
-  P->last_iters = h.iter;
-  P->last_status = h.done ? h.status : ETC_NOT_CONVERGED;
+  int iters = 0, status = ST_OK;
+  for (int i = 0; i < P->nseg; ++i) {
+    const DevState& h = P->st_host[i];
+    iters = std::max(iters, h.iter);
+    const int st = h.done ? h.status : ST_NOT_CONVERGED;
+    if (st == ST_BREAKDOWN) status = ST_BREAKDOWN;
+    else if (st == ST_NOT_CONVERGED && status == ST_OK) status = ST_NOT_CONVERGED;
+  }
+  P->last_iters = iters;
+  P->last_status = status;
   if (P->timer_id > 0) {
     double tot = 0.0;
     for (int i = 0; i + 1 < P->ev_used; i += 2) {
@@ -963,12 +1043,12 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
     P->timer_launches = P->ev_used / 2;
   }
   if (res) {
-    res->iters = h.iter;
+    res->iters = P->st_host[0].iter;
     res->status = P->last_status;
-    res->relres = h.relres;
+    res->relres = P->st_host[0].relres;
     for (int i = 0; i < 5; ++i) res->kref[i] = P->kref[i];
-    res->lambda_lo = P->lam_lo;
-    res->lambda_hi = P->lam_hi;
+    res->lambda_lo = P->lam_lo[0];
+    res->lambda_hi = P->lam_hi[0];
   }
   if (P->last_status == ST_BREAKDOWN) {
     P->solved = false;
@@ -982,41 +1062,74 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
   return ETC_OK;
 }
 
+etc_status etc_batch_results(const etc_plan* P, int* iters, int* status, double* relres) {
+  if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  for (int i = 0; i < P->nseg; ++i) {
+    const DevState& h = P->st_host[i];
+    if (iters) iters[i] = h.iter;
+    if (status) status[i] = h.done ? h.status : ST_NOT_CONVERGED;
+    if (relres) relres[i] = h.relres;
+  }
+  return ETC_OK;
+}
+
+static etc_status keff_all(etc_plan* P, bool energy) {
+  if (!P->solved) return fail(ETC_E_STATE, "etc_keff before a successful etc_solve");
+  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::keff(P, energy) : Ops<double>::keff(P, energy);
+  if (s) return s;
+  return pull_state(P);
+}
+
 etc_status etc_keff(etc_plan* P, double* k_out, double* k_in, double* k_energy) {
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
-  if (!P->solved) return fail(ETC_E_STATE, "etc_keff before a successful etc_solve");
   if (!k_out) return fail(ETC_E_INVALID, "k_out is NULL");
-  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::keff(P, k_energy != nullptr)
-                                        : Ops<double>::keff(P, k_energy != nullptr);
+  etc_status s = keff_all(P, k_energy != nullptr);
   if (s) return s;
-  HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
   const Geo& g = P->g;
   const double dp = g.p_in - g.p_out;
   const double scale = (double)g.nL / ((double)g.na * (double)g.nb * dp);
-  *k_out = scale * P->st_host->k_acc[0];
-  if (k_in) *k_in = scale * P->st_host->k_acc[1];
-  if (k_energy) *k_energy = scale / g.fL * P->st_host->k_acc[2] / dp;
+  *k_out = scale * P->st_host[0].k_acc[0];
+  if (k_in) *k_in = scale * P->st_host[0].k_acc[1];
+  if (k_energy) *k_energy = scale / g.fL * P->st_host[0].k_acc[2] / dp;
+  return ETC_OK;
+}
+
+etc_status etc_keff_batch(etc_plan* P, double* k_out, double* k_in) {
+  if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (!k_out) return fail(ETC_E_INVALID, "k_out is NULL");
+  etc_status s = keff_all(P, false);
+  if (s) return s;
+  const Geo& g = P->g;
+  const double scale = (double)g.nL / ((double)g.na * (double)g.nb * (g.p_in - g.p_out));
+  for (int i = 0; i < P->nseg; ++i) {
+    k_out[i] = scale * P->st_host[i].k_acc[0];
+    if (k_in) k_in[i] = scale * P->st_host[i].k_acc[1];
+  }
   return ETC_OK;
 }
 
 etc_status etc_get_solution(const etc_plan* P, double* p) {
   if (!P || !p) return fail(ETC_E_INVALID, "NULL argument");
   if (!P->solved) return fail(ETC_E_STATE, "etc_get_solution before a successful etc_solve");
-  const Geo& g = P->g;
-  if (P->axis == 2) {
-    dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
-    k_decanon_axis2<<<grid, dim3(32, 8), 0, P->stream>>>(P->p, p, g);
-  } else {
-    k_decanon_rows<<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->p, p, P->axis, g);
+  Geo g = P->g;
+  g.nseg = 1;
+  for (int inst = 0; inst < P->nseg; ++inst) {
+    const double* src = P->p + (int64_t)inst * g.V;
+    double* dst = p + (int64_t)inst * g.V;
+    if (P->axis == 2) {
+      dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+      k_decanon_axis2<<<grid, dim3(32, 8), 0, P->stream>>>(src, dst, g);
+    } else {
+      k_decanon_rows<<<P->lc.nStride, kThreads, 0, P->stream>>>(src, dst, P->axis, g);
+    }
+    LAUNCHCHK("decanon");
   }
-  LAUNCHCHK("decanon");
   return ETC_OK;
 }
 
 etc_status etc_residual_history(const etc_plan* P, double* hist, int cap, int* count) {
   if (!P || !hist || !count) return fail(ETC_E_INVALID, "NULL argument");
-  int n = std::min(cap, P->last_iters + 1);
+  int n = std::min(cap, P->st_host[0].iter + 1);
   if (n < 0) n = 0;
   if (n > 0) {
     HIPCHK(hipMemcpyAsync(hist, P->hist, n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
@@ -1034,6 +1147,7 @@ etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
   const Geo g0 = P->g;
   const int iters0 = P->last_iters, status0 = P->last_status;
   const int timer0 = P->timer_id;
+  std::vector<DevState> st0(P->st_host, P->st_host + P->nseg);
   std::swap(P->p, P->padj);
   P->g.p_in = 0.0;
   P->g.p_out = 1.0;
@@ -1044,6 +1158,7 @@ etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
   P->timer_id = timer0;
   P->last_iters = iters0;
   P->last_status = status0;
+  std::copy(st0.begin(), st0.end(), P->st_host);
   P->solved = true;
   if (s != ETC_OK && s != ETC_NOT_CONVERGED) return s;
   const double c = (double)g0.nL / ((double)g0.na * (double)g0.nb * (g0.p_in - g0.p_out));
@@ -1060,9 +1175,10 @@ etc_status etc_apply_A(etc_plan* P, const void* x, void* y, double* xAx) {
                                         : Ops<double>::apply_A(P, x, y, xAx != nullptr);
   if (s) return s;
   if (xAx) {
-    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
-    HIPCHK(hipStreamSynchronize(P->stream));
-    *xAx = P->st_host->k_acc[3];
+    if ((s = pull_state(P))) return s;
+    double sum = 0.0;
+    for (int i = 0; i < P->nseg; ++i) sum += P->st_host[i].k_acc[3];
+    *xAx = sum;
   }
   return ETC_OK;
 }
@@ -1071,7 +1187,7 @@ etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
   if (!P || !r || !z) return fail(ETC_E_INVALID, "NULL argument");
   if (r == z) return fail(ETC_E_INVALID, "r and z must not alias");
   if (P->opt.precond == ETC_PC_NONE) {
-    HIPCHK(hipMemcpyAsync(z, r, (size_t)P->g.V * elt_size(P->prec), hipMemcpyDeviceToDevice, P->stream));
+    HIPCHK(hipMemcpyAsync(z, r, (size_t)P->g.V * P->nseg * elt_size(P->prec), hipMemcpyDeviceToDevice, P->stream));
     if (rz) return fail(ETC_E_UNSUPPORTED, "no dot without a preconditioner");
     return ETC_OK;
   }
@@ -1079,9 +1195,10 @@ etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
                                         : Ops<double>::precond(P, (const double*)r, (double*)z, 0, P->st, 0, FIN_ACC3);
   if (s) return s;
   if (rz) {
-    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState), hipMemcpyDeviceToHost, P->stream));
-    HIPCHK(hipStreamSynchronize(P->stream));
-    *rz = P->st_host->k_acc[3];
+    if ((s = pull_state(P))) return s;
+    double sum = 0.0;
+    for (int i = 0; i < P->nseg; ++i) sum += P->st_host[i].k_acc[3];
+    *rz = sum;
   }
   return ETC_OK;
 }

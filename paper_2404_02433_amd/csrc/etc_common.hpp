@@ -10,15 +10,17 @@ namespace etc {
 struct Geo {
   int nL, na, nb;
   int64_t plane;      // na * nb
-  int64_t V;          // nL * na * nb
+  int64_t V;          // nL * na * nb (one instance)
+  int nseg;           // instances stacked along the load axis (a batch of same-size RVEs)
   double fL, fa, fb;  // 1 / h^2 per canonical axis (scaled conductivity factors)
   double p_in, p_out;
 };
 
-// Reference-medium parameters and per-mode eigenvalue tables of the
-// preconditioner (tridiagonal shift lambda_a * ka + lambda_b * kb).
+// Reference-medium parameters (per instance: kL ka kb kin kout) and per-mode
+// eigenvalue tables of the preconditioner (tridiagonal shift
+// lambda_a * ka + lambda_b * kb).
 struct RefMedium {
-  double kL, ka, kb, kin, kout;
+  const double* kref;   // 5 per instance
   const double* lam_a;  // length na, 4 sin^2(pi a' / (2 na))
   const double* lam_b;  // length nb
 };

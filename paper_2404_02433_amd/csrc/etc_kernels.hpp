@@ -35,6 +35,15 @@ template <class S> struct Kap {
   __device__ __forceinline__ double dL(int64_t i) const { return hL ? hL[i] : (double)L[i]; }
   __device__ __forceinline__ double dA(int64_t i) const { return hA ? hA[i] : (double)A[i]; }
   __device__ __forceinline__ double dB(int64_t i) const { return hB ? hB[i] : (double)B[i]; }
+  // view of instance s of a batch (instances are V voxels apart)
+  __device__ __forceinline__ void shift(int64_t off) {
+    L += off;
+    A += off;
+    B += off;
+    if (hL) hL += off;
+    if (hA) hA += off;
+    if (hB) hB += off;
+  }
 };
 
 // Right-hand-side data beyond the constant Dirichlet pair, all nullable:
@@ -198,6 +207,15 @@ template <class S>
 __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* __restrict__ r, Kap<S> kp, Rhs rh,
                                               S* __restrict__ dlt, double* __restrict__ partials) {
   __shared__ double red[16];
+  // instance blockIdx.y of a batch
+  {
+    const int64_t off = (int64_t)blockIdx.y * g.V;
+    p += off;
+    r += off;
+    if (dlt) dlt += off;
+    kp.shift(off);
+    partials += (int64_t)blockIdx.y * gridDim.x;
+  }
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
@@ -222,14 +240,24 @@ template <class S, class C, bool ORTHO>
 __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w, Kap<S> kp, S* __restrict__ q,
                                                  double* __restrict__ partials, const DevState* __restrict__ st,
                                                  int gate, int kchunk) {
+  // blockIdx.z = instance * chunks + chunk (instances of a batch are V apart)
+  const int nch = (g.nL + kchunk - 1) / kchunk;
+  const int inst = blockIdx.z / nch, chunk = blockIdx.z - inst * nch;
+  if (st) st += inst;
   if (gated_out(st, gate)) return;
+  {
+    const int64_t off = (int64_t)inst * g.V;
+    w += off;
+    q += off;
+    kp.shift(off);
+  }
   // planes loaded per step: KU planes of w and kappa are requested together
   // so each thread keeps several HBM loads in flight along the k march
   constexpr int KU = 4;
   __shared__ double red[16];
   const int b = blockIdx.x * 64 + threadIdx.x;
   const int a = blockIdx.y * 4 + threadIdx.y;
-  const int k0 = blockIdx.z * kchunk;
+  const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
   const bool valid = (a < g.na) && (b < g.nb);
   const S* __restrict__ ks = kp.L;
@@ -301,11 +329,21 @@ template <class S, bool ORTHO>
 __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
                                                   S* __restrict__ r, double* __restrict__ partials,
                                                   const DevState* __restrict__ st, int gate, int kchunk) {
+  const int nch = (g.nL + kchunk - 1) / kchunk;
+  const int inst = blockIdx.z / nch, chunk = blockIdx.z - inst * nch;
+  if (st) st += inst;
   if (gated_out(st, gate)) return;
+  {
+    const int64_t off = (int64_t)inst * g.V;
+    p += off;
+    r += off;
+    kp.shift(off);
+    if (rh.src) rh.src += off;
+  }
   __shared__ double red[16];
   const int b = blockIdx.x * 64 + threadIdx.x;
   const int a = blockIdx.y * 4 + threadIdx.y;
-  const int k0 = blockIdx.z * kchunk;
+  const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
   const bool valid = (a < g.na) && (b < g.nb);
   double acc = 0.0;
@@ -370,7 +408,21 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
                                                   S* __restrict__ p, const S* __restrict__ w, S* __restrict__ r,
                                                   const S* __restrict__ q, double* __restrict__ partials,
                                                   const DevState* __restrict__ st, int gate) {
+  // instance blockIdx.y of a batch
+  if (st) st += blockIdx.y;
   if (gated_out(st, gate)) return;
+  {
+    const int64_t off = (int64_t)blockIdx.y * g.V;
+    if (src) src += off;
+    dst += off;
+    if (MODE == 1) {
+      p += off;
+      w += off;
+      r += off;
+      q += off;
+      partials += (int64_t)blockIdx.y * gridDim.x;
+    }
+  }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   __shared__ double red[16];
@@ -460,7 +512,13 @@ template <class S, class T, int MODE>
 __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
                                                   const DevState* __restrict__ st, int gate) {
+  if (st) st += blockIdx.y;
   if (gated_out(st, gate)) return;
+  {
+    const int64_t off = (int64_t)blockIdx.y * g.V;
+    src += off;
+    dst += off;
+  }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -553,6 +611,8 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
 template <class S, class T, int DIR>
 __global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
                                               int tb, const DevState* __restrict__ st, int gate) {
+  // blockIdx.y = global plane; instances of a batch hold nL planes each
+  if (st) st += blockIdx.y / g.nL;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -693,7 +753,12 @@ template <class S, int TB, int P, int MAXM>
 __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
                                                   int gate) {
+  // instance blockIdx.z of a batch
+  if (st) st += blockIdx.z;
   if (gated_out(st, gate)) return;
+  t += (int64_t)blockIdx.z * g.V;
+  if (partials) partials += (int64_t)blockIdx.z * gridDim.x * gridDim.y;
+  const double* kr = rm.kref + 5 * blockIdx.z;
   __shared__ double sh[8][P][TB];  // yF yL m11 mmm m1m ts|c' Dsep|d' x
   __shared__ double red[16];
   const int tid = threadIdx.x;
@@ -709,11 +774,11 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
   const bool has_right = active && (p < Peff - 1);
   const int endp = min(start + m, nL);
   const int len = active ? (endp - start - (has_right ? 1 : 0)) : 0;
-  const double kL = rm.kL;
-  const double s = line_ok ? (rm.lam_a[am] * rm.ka + rm.lam_b[bm] * rm.kb) : 0.0;
+  const double kL = kr[0];
+  const double s = line_ok ? (rm.lam_a[am] * kr[1] + rm.lam_b[bm] * kr[2]) : 0.0;
   const double aoff = -kL;
   const double a2 = kL * kL;
-  const double Dint = s + 2.0 * kL, D0 = s + kL + 2.0 * rm.kin, DN = s + kL + 2.0 * rm.kout;
+  const double Dint = s + 2.0 * kL, D0 = s + kL + 2.0 * kr[3], DN = s + kL + 2.0 * kr[4];
   auto Dof = [&](int k) { return k == 0 ? D0 : (k == nL - 1 ? DN : Dint); };
 
   const int64_t col = (int64_t)am * g.nb + bm;
@@ -842,9 +907,14 @@ enum FinOp { FIN_BNORM = 0, FIN_RHO0, FIN_ALPHA, FIN_RR, FIN_REFINE, FIN_BETA, F
 
 // One block of 1024 threads sums n partials in a fixed order and applies the
 // scalar step of the iteration to the device state.
-__global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__ partials, int n, DevState* st,
-                                              double* __restrict__ hist) {
+// Block s handles instance s of a batch: partials + s * pstride, state s,
+// history row s (hstride entries).
+__global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__ partials, int n, int64_t pstride,
+                                              DevState* st, double* __restrict__ hist, int hstride) {
   __shared__ double red[16];
+  partials += (int64_t)blockIdx.x * pstride;
+  st += blockIdx.x;
+  hist += (int64_t)blockIdx.x * hstride;
   if (op == FIN_REFINE) {
     if (st->done || !st->refine) return;
   } else if (op == FIN_ALPHA || op == FIN_RR || op == FIN_BETA || op == FIN_RHO0) {
@@ -959,6 +1029,10 @@ template <class S>
 __global__ __launch_bounds__(256) void k_keff(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
                                               double* __restrict__ partials) {
   __shared__ double red[16];
+  // instance blockIdx.y: partials [instance][2][gridDim.x]
+  p += (int64_t)blockIdx.y * g.V;
+  kp.shift((int64_t)blockIdx.y * g.V);
+  partials += (int64_t)blockIdx.y * 2 * gridDim.x;
   double ao = 0.0, ai = 0.0;
   const int64_t last = (int64_t)(g.nL - 1) * g.plane;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.plane; i += (int64_t)gridDim.x * blockDim.x) {
@@ -980,6 +1054,9 @@ template <class S>
 __global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
                                                 double* __restrict__ partials) {
   __shared__ double red[16];
+  p += (int64_t)blockIdx.y * g.V;
+  kp.shift((int64_t)blockIdx.y * g.V);
+  partials += (int64_t)blockIdx.y * gridDim.x;
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
@@ -1023,6 +1100,13 @@ __global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict_
 template <class S>
 __global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ p, const double* __restrict__ phi,
                                               Kap<S> kp, double c, int axis, double* __restrict__ out) {
+  {
+    const int64_t off = (int64_t)blockIdx.y * g.V;
+    p += off;
+    phi += off;
+    kp.shift(off);
+    out += off;
+  }
   const double lsc = c / g.fL;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
@@ -1054,7 +1138,16 @@ template <class S>
 __global__ __launch_bounds__(256) void k_update_plain(Geo g, S* __restrict__ p, const S* __restrict__ w,
                                                       S* __restrict__ r, const S* __restrict__ q,
                                                       double* __restrict__ partials, const DevState* __restrict__ st) {
+  st += blockIdx.y;
   if (st->done) return;
+  {
+    const int64_t off = (int64_t)blockIdx.y * g.V;
+    p += off;
+    w += off;
+    r += off;
+    q += off;
+    partials += (int64_t)blockIdx.y * gridDim.x;
+  }
   __shared__ double red[16];
   const double alpha = st->alpha;
   double acc = 0.0;
@@ -1073,7 +1166,10 @@ __global__ __launch_bounds__(256) void k_update_plain(Geo g, S* __restrict__ p, 
 template <class S>
 __global__ __launch_bounds__(256) void k_norm2(Geo g, const S* __restrict__ x, double* __restrict__ partials,
                                                const DevState* __restrict__ st) {
+  if (st) st += blockIdx.y;
   if (st && st->done) return;
+  x += (int64_t)blockIdx.y * g.V;
+  partials += (int64_t)blockIdx.y * gridDim.x;
   __shared__ double red[16];
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1087,7 +1183,10 @@ __global__ __launch_bounds__(256) void k_norm2(Geo g, const S* __restrict__ x, d
 template <class S>
 __global__ __launch_bounds__(256) void k_dir_plain(Geo g, const S* __restrict__ r, S* __restrict__ w,
                                                    const DevState* __restrict__ st, int init) {
+  st += blockIdx.y;
   if (st->done) return;
+  r += (int64_t)blockIdx.y * g.V;
+  w += (int64_t)blockIdx.y * g.V;
   const double beta = st->beta;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride)
@@ -1097,7 +1196,10 @@ __global__ __launch_bounds__(256) void k_dir_plain(Geo g, const S* __restrict__ 
 // Mixed form, at a refinement: p += increment, increment = 0 (float64 p).
 __global__ __launch_bounds__(256) void k_flush(Geo g, double* __restrict__ p, float* __restrict__ dlt,
                                                const DevState* __restrict__ st) {
+  st += blockIdx.y;
   if (st->done || !st->refine) return;
+  p += (int64_t)blockIdx.y * g.V;
+  dlt += (int64_t)blockIdx.y * g.V;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
     p[i] += (double)dlt[i];

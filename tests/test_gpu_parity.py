@@ -373,3 +373,42 @@ def test_reference_parameter_modes_reach_the_same_keff():
         assert o["status"] == "ok"
         assert abs(o["keff"] - mid["keff"]) < 1e-7 * mid["keff"]
     assert one["kref"] == [1.0] * 5
+
+
+# ----------------------------------------------------------------- batches
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_individual_solves(precision):
+    """A batch of same-size RVEs in one plan: every instance reaches the K_eff
+    of its own solve; per-instance exit tests (the instances converge after
+    different pass counts)."""
+    n = 24
+    kaps = [np.exp(s * np.random.default_rng(100 + i).standard_normal((n, n, n))) for i, s in
+            enumerate([0.2, 0.6, 1.0, 1.4, 0.1])]
+    batch = dev(np.stack(kaps))
+    rtol = 1e-10 if precision == "fp64" else 1e-6
+    out = etc.solve_batch(batch, 0, precision=precision, rtol=rtol)
+    assert out["status"] == "ok"
+    assert len(set(out["iters"])) > 1
+    for i, k in enumerate(kaps):
+        ref = O.solve(k, 0, rtol=1e-12)
+        tol = 1e-8 if precision == "fp64" else 1e-5
+        assert abs(out["keff"][i] - ref["keff"]) <= tol * ref["keff"], (i, out["keff"][i], ref["keff"])
+        single = etc.solve(dev(k), 0, precision=precision, rtol=rtol)
+        assert out["iters"][i] == single["iters"]
+        if precision == "fp64":
+            assert out["keff"][i] == single["keff"]   # same reductions, same order
+
+
+def test_batch_solution_and_gradient_layout():
+    n = (10, 12, 14)
+    kaps = np.stack([np.exp(0.5 * np.random.default_rng(7 + i).standard_normal(n)) for i in range(3)])
+    plan = etc.etc_setup_batch(dev(kaps), 2, rtol=1e-12, want_grad=True)
+    etc.etc_solve(plan)
+    p = etc.etc_get_solution(plan).cpu().numpy()
+    g = etc.etc_grad(plan).cpu().numpy()
+    plan.close()
+    for i in range(3):
+        ref = O.solve(kaps[i], 2, rtol=1e-13)
+        assert np.abs(p[i] - O.decanonical(ref["pcg"].p, 2)).max() < 1e-9
+        gref = O.decanonical(O.keff_gradient(ref["problem"], ref["pcg"].p), 2)
+        assert np.abs(g[i] - gref).max() < 1e-8 * np.abs(gref).max()
