@@ -16,9 +16,11 @@ Everything is float64 NumPy, written to be read against the paper:
   h = L/N); the scaled coefficients are kappa~ = kappa / h^2 (Section
   "Discretization scheme", scaling before eq:scaled bilinear forms).
 
-Parity status of each function (pins live in ``tests/test_oracle_*.py``):
-every public function is pinned except ``kref_lp_scipy``-free helpers noted
-"helper" below.
+Every public function is pinned by ``tests/test_oracle_pins.py`` against
+facts the paper or mathematics fix (library transforms, dense solves, exact
+laminate and homogeneous cases, bounds, the spectral lemma, the LP optimum,
+Tables 1 and 2, finite differences); the layout helpers marked "helper"
+only move axes.
 """
 
 from __future__ import annotations
