@@ -38,23 +38,26 @@ etc_status fail(etc_status s, const std::string& msg) {
 constexpr int kThreads = 256;
 constexpr int kMaxGridStride = 2048;   // grid of the grid-stride reduction kernels
 constexpr int kThomasP = 32;           // partitions per line in the tridiagonal kernel
-constexpr int kThomasTB = 16;          // modes (lines) per tridiagonal block
+constexpr int kThomasTB = 16;          // modes (lines) per tridiagonal block, float64 (128-byte rows)
+constexpr int kThomasTBf = 32;         // float32: 32 modes keep whole 128-byte rows
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Launch shapes.  Every grid carries the instance index of a batch in its
 // last dimension; nX is the number of blocks (= partial sums) per instance.
 struct LaunchCfg {
-  // operator / residual: block (64, 4), k chunk
+  // operator: block (64, 4) over 64 x 16 tiles; residual: 64 x 4 tiles
   dim3 gridA;
   int kchunk, nA;
+  dim3 gridR;
+  int kchunkR, nR;
   // rows
   int rpb, nrows;
   dim3 gridRows;
   int nRows;
   size_t ldsRows;
   // columns
-  int tb;
+  int tb, colThreads;
   dim3 gridCols;
   size_t ldsCols;
   // tridiagonal
@@ -171,15 +174,25 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   LaunchCfg lc{};
   const size_t cx_sz = 2 * elt;
   const int ns = g.nseg;
-  // operator: aim for >= ~4096 blocks over the whole batch
-  const int gx = (g.nb + 63) / 64, gy = (g.na + 3) / 4;
+  // operator (tiles of 64 b x 16 a; the residual kernel keeps 64 x 4): aim for
+  // >= ~2048 blocks over the whole batch
+  const int gx = (g.nb + 63) / 64, gy = (g.na + 15) / 16;
   const int64_t cols = (int64_t)gx * gy * ns;
   int kchunk = g.nL;
-  while (kchunk > 8 && cols * ((g.nL + kchunk - 1) / kchunk) < 4096) kchunk = (kchunk + 1) / 2;
+  while (kchunk > 16 && cols * ((g.nL + kchunk - 1) / kchunk) < 2048) kchunk = (kchunk + 1) / 2;
   const int nch = (g.nL + kchunk - 1) / kchunk;
   lc.kchunk = kchunk;
   lc.gridA = dim3(gx, gy, nch * ns);
   lc.nA = gx * gy * nch;
+  {
+    const int gy4 = (g.na + 3) / 4;
+    int kc4 = g.nL;
+    while (kc4 > 8 && (int64_t)gx * gy4 * ns * ((g.nL + kc4 - 1) / kc4) < 4096) kc4 = (kc4 + 1) / 2;
+    const int nch4 = (g.nL + kc4 - 1) / kc4;
+    lc.kchunkR = kc4;
+    lc.gridR = dim3(gx, gy4, nch4 * ns);
+    lc.nR = gx * gy4 * nch4;
+  }
   // rows (b axis)
   {
     const size_t line_bytes = (size_t)dpb.lstride * cx_sz;
@@ -197,7 +210,10 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   {
     const size_t line_bytes = (size_t)dpa.lstride * cx_sz;
     int tb = (int)std::max<size_t>(1, (80 * 1024) / line_bytes);
-    if (dpa.fft) tb = std::min(tb, std::max(1, 16 * kThreads / dpa.M));
+    // float32 columns use 512-thread blocks so 32-wide tiles (128-byte rows)
+    // still fit one pass per FFT stage (16 complex values per thread)
+    lc.colThreads = (elt == 4) ? 2 * kThreads : kThreads;
+    if (dpa.fft) tb = std::min(tb, std::max(1, 16 * lc.colThreads / dpa.M));
     tb = std::min(tb, 32);
     if (tb >= 16) tb = 16 * (tb / 16);
     else if (tb >= 8) tb = 8;
@@ -212,7 +228,8 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     int m = (g.nL + Puse - 1) / Puse;
     lc.Puse = Puse;
     lc.maxm = m;
-    lc.gridThomas = dim3((g.nb + kThomasTB - 1) / kThomasTB, g.na, ns);
+    const int tbm = elt == 4 ? kThomasTBf : kThomasTB;
+    lc.gridThomas = dim3((g.nb + tbm - 1) / tbm, g.na, ns);
     lc.nThomas = lc.gridThomas.x * lc.gridThomas.y;
   }
   int64_t gs = (g.V + kThreads - 1) / kThreads;
@@ -228,6 +245,7 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
 int max_partials_of(const LaunchCfg& lc) {
   int64_t m = 1024;
   m = std::max<int64_t>(m, lc.nA);
+  m = std::max<int64_t>(m, lc.nR);
   m = std::max<int64_t>(m, lc.nRows);
   m = std::max<int64_t>(m, lc.nThomas);
   m = std::max<int64_t>(m, (int64_t)lc.nStride * 12);
@@ -430,13 +448,14 @@ template <class S> struct Ops {
   static etc_status thomas(etc_plan* P, S* t, double* partials, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     const RefMedium rm = ref(P);
-    const int threads = kThomasTB * kThomasP;
+    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
+    const int threads = TB * kThomasP;
     if (lc.maxm <= 16)
-      k_thomas<S, kThomasTB, kThomasP, 16><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+      k_thomas<S, TB, kThomasP, 16><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
     else if (lc.maxm <= 32)
-      k_thomas<S, kThomasTB, kThomasP, 32><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+      k_thomas<S, TB, kThomasP, 32><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
     else
-      k_thomas<S, kThomasTB, kThomasP, 64><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+      k_thomas<S, TB, kThomasP, 64><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
     LAUNCHCHK("thomas");
     return ETC_OK;
   }
@@ -470,13 +489,13 @@ template <class S> struct Ops {
     k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
         P->g, P->dpb, twb, src, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, st, gate);
     LAUNCHCHK("rows_fwd");
-    k_cols<S, T, -1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
+    k_cols<S, T, -1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
     LAUNCHCHK("cols_fwd");
     etc_status s = thomas(P, t, P->partials, st, gate);
     if (s) return s;
     s = fin(P, fin_op, lc.nThomas, lc.nThomas);
     if (s) return s;
-    k_cols<S, T, +1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
+    k_cols<S, T, +1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
     LAUNCHCHK("cols_inv");
     if (inv_mode == 1)
       k_rows_inv<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, t, dst, lc.rpb,
@@ -507,7 +526,7 @@ template <class S> struct Ops {
       s = residual(P, r, nullptr, 0);
       if (s) return s;
       // relative residual of the warm start
-      if ((s = fin(P, FIN_RR0, lc.nA, lc.nA))) return s;
+      if ((s = fin(P, FIN_RR0, lc.nR, lc.nR))) return s;
     }
     if (P->opt.precond == ETC_PC_NONE) {
       k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
@@ -546,7 +565,7 @@ template <class S> struct Ops {
     if (P->prec == ETC_MIXED) {
       if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
-      if ((s = fin(P, FIN_REFINE, lc.nA, lc.nA))) return s;
+      if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
     }
     k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
     LAUNCHCHK("norm2");
@@ -587,13 +606,13 @@ template <class S> struct Ops {
       // when requested, and redo DCT_b
       if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
-      if ((s = fin(P, FIN_REFINE, lc.nA, lc.nA))) return s;
+      if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
       k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
           g, P->dpb, twb, r, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
       LAUNCHCHK("rows_fwd_refine");
     }
     timer_begin(P, 3);
-    k_cols<S, T, -1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
+    k_cols<S, T, -1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
     timer_end(P, 3);
     LAUNCHCHK("cols_fwd");
     timer_begin(P, 4);
@@ -602,7 +621,7 @@ template <class S> struct Ops {
     if (s) return s;
     if ((s = fin(P, FIN_BETA, lc.nThomas, lc.nThomas))) return s;
     timer_begin(P, 5);
-    k_cols<S, T, +1><<<lc.gridCols, kThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
+    k_cols<S, T, +1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
     timer_end(P, 5);
     LAUNCHCHK("cols_inv");
     // w = DCT_b^{-1}(t) + beta w
@@ -648,11 +667,11 @@ template <class S> struct Ops {
   static etc_status residual(etc_plan* P, S* r, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     if (P->ortho)
-      k_residual<S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
-                                                                   lc.kchunk);
+      k_residual<S, true><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
+                                                                   lc.kchunkR);
     else
-      k_residual<S, false><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st,
-                                                                    gate, lc.kchunk);
+      k_residual<S, false><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st,
+                                                                    gate, lc.kchunkR);
     LAUNCHCHK("residual");
     return ETC_OK;
   }

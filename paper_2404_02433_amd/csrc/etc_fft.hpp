@@ -154,14 +154,18 @@ template <int R, int DIR, class T> __device__ __forceinline__ void dftR(cx<T>* v
 // One radix-R stage over `lines` lines of M complex values (LDS, padded),
 // line stride `ls` (complex units).  `tw[j]` = exp(-2 pi i j / (8M)).
 // Every thread must call it (it contains barriers).
-template <int R> struct ipt_of {
-  static constexpr int v = (R >= 16) ? 1 : (16 / R);
+// Complex values a thread may hold in one stage.
+template <class T> struct stage_cap {
+  static constexpr int v = 16;
+};
+template <class T, int R> struct ipt_of {
+  static constexpr int v = (R >= stage_cap<T>::v) ? 1 : (stage_cap<T>::v / R);
 };
 
 // Items per thread of a radix-R stage: a stage over `lines` lines of M points
-// fits one pass when lines * M <= 16 * nthr.  Not inlined, so each radix gets
-// its own register allocation.
-template <class T, int R, int DIR, int IPT = ipt_of<R>::v>
+// fits one pass when lines * M <= stage_cap * nthr.  Not inlined, so each
+// radix gets its own register allocation.
+template <class T, int R, int DIR, int IPT = ipt_of<T, R>::v>
 __device__ __attribute__((noinline)) void fft_stage(cx<T>* buf, int lines, int ls, int M, int Ns, const cx<T>* __restrict__ tw,
                                           int tid, int nthr) {
   const int per_line = M / R;

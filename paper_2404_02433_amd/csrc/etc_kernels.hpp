@@ -236,6 +236,15 @@ __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* 
 // with the partial w . q of each block.  Block (64, 4) covers 64 b x 4 a
 // columns and marches along k over `kchunk` planes keeping the k-1, k, k+1
 // values in registers; lateral neighbours come through the caches.
+// 2.5D tiling: a block of 64 x 4 threads owns a tile of 64 (b) x 16 (a)
+// columns (4 rows per thread) and marches along k over `kchunk` planes.  The
+// current plane of w and kappa sits in LDS with a one-voxel halo (lateral
+// neighbours); planes k-1 and k+1 stay in registers.  Tile centres are
+// prefetched two planes ahead and halos one plane ahead, so every HBM value is
+// read once per sweep plus the halo rows.  (ORTHO: the a and b faces use their
+// own conductivity components, read from the caches.)
+constexpr int ATB = 64, ATA = 16, ARPT = 4;  // tile width (b), height (a), rows per thread
+
 template <class S, class C, bool ORTHO>
 __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w, Kap<S> kp, S* __restrict__ q,
                                                  double* __restrict__ partials, const DevState* __restrict__ st,
@@ -251,71 +260,115 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
     q += off;
     kp.shift(off);
   }
-  // planes loaded per step: KU planes of w and kappa are requested together
-  // so each thread keeps several HBM loads in flight along the k march
-  constexpr int KU = 4;
+  __shared__ C tw_[ATA + 2][ATB + 2];
+  __shared__ C tk_[ATA + 2][ATB + 2];
   __shared__ double red[16];
-  const int b = blockIdx.x * 64 + threadIdx.x;
-  const int a = blockIdx.y * 4 + threadIdx.y;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int b0 = blockIdx.x * ATB, a0 = blockIdx.y * ATA;
+  const int b = b0 + tx;
   const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
-  const bool valid = (a < g.na) && (b < g.nb);
   const S* __restrict__ ks = kp.L;
   const S* __restrict__ ka = ORTHO ? kp.A : kp.L;
   const S* __restrict__ kb = ORTHO ? kp.B : kp.L;
+  const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
+  const bool bok = b < g.nb;
+  bool rok[ARPT];
+  int64_t col[ARPT];
+#pragma unroll
+  for (int j = 0; j < ARPT; ++j) {
+    const int a = a0 + ty + 4 * j;
+    rok[j] = bok && a < g.na;
+    col[j] = (int64_t)a * g.nb + b;
+  }
+  // halo element of this thread: top row (ty 0), bottom row (ty 1), left
+  // column (ty 2, tx < 16), right column (ty 3, tx < 16)
+  int hr = -1, hc = -1;
+  int64_t hcol = 0;
+  {
+    int ha = -1, hb = -1;
+    if (ty == 0) { ha = a0 - 1; hb = b; hr = 0; hc = tx + 1; }
+    else if (ty == 1) { ha = a0 + ATA; hb = b; hr = ATA + 1; hc = tx + 1; }
+    else if (tx < ATA) { ha = a0 + tx; hb = (ty == 2) ? b0 - 1 : b0 + ATB; hr = tx + 1; hc = (ty == 2) ? 0 : ATB + 1; }
+    if (ha < 0 || ha >= g.na || hb < 0 || hb >= g.nb) hr = -1;
+    else hcol = (int64_t)ha * g.nb + hb;
+  }
+  auto ld = [&](const S* __restrict__ arr, int k, int64_t c, bool ok, C dflt) -> C {
+    return (ok && k >= 0 && k < g.nL) ? (C)arr[(int64_t)k * g.plane + c] : dflt;
+  };
+  C wm[ARPT], km[ARPT], wc[ARPT], kc[ARPT], wn[ARPT], kn[ARPT];
+#pragma unroll
+  for (int j = 0; j < ARPT; ++j) {
+    wm[j] = ld(w, k0 - 1, col[j], rok[j], C(0));
+    km[j] = ld(ks, k0 - 1, col[j], rok[j], C(1));
+    wc[j] = ld(w, k0, col[j], rok[j], C(0));
+    kc[j] = ld(ks, k0, col[j], rok[j], C(1));
+    wn[j] = ld(w, k0 + 1, col[j], rok[j], C(0));
+    kn[j] = ld(ks, k0 + 1, col[j], rok[j], C(1));
+  }
+  C hw = ld(w, k0, hcol, hr >= 0, C(0)), hk = ld(ks, k0, hcol, hr >= 0, C(1));
   double acc = 0.0;
-  if (valid) {
-    const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
-    const int64_t col = (int64_t)a * g.nb + b;
-    const bool has_am = a > 0, has_ap = a + 1 < g.na, has_bm = b > 0, has_bp = b + 1 < g.nb;
-    int64_t i = (int64_t)k0 * g.plane + col;
-    C wc = (C)w[i], kc = (C)ks[i];
-    C wm = C(0), km = C(1);
-    if (k0 > 0) {
-      wm = (C)w[i - g.plane];
-      km = (C)ks[i - g.plane];
-    }
-    for (int k = k0; k < k1; k += KU) {
-      // next KU planes (plane k+1+u), guarded by the grid
-      C wn[KU], kn[KU];
+  for (int k = k0; k < k1; ++k) {
+    // prefetch: centres of plane k+2, halo of plane k+1
+    C wnn[ARPT], knn[ARPT];
+    const bool more = k + 1 < k1;
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const int kk = k + 1 + u;
-        if (kk < g.nL && kk <= k1) {
-          wn[u] = (C)w[i + (int64_t)(u + 1) * g.plane];
-          kn[u] = (C)ks[i + (int64_t)(u + 1) * g.plane];
+    for (int j = 0; j < ARPT; ++j) {
+      wnn[j] = ld(w, k + 2, col[j], rok[j] && more, C(0));
+      knn[j] = ld(ks, k + 2, col[j], rok[j] && more, C(1));
+    }
+    const C hwn = ld(w, k + 1, hcol, hr >= 0 && more, C(0)), hkn = ld(ks, k + 1, hcol, hr >= 0 && more, C(1));
+    __syncthreads();  // previous plane's LDS reads are done
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      tw_[1 + ty + 4 * j][1 + tx] = wc[j];
+      tk_[1 + ty + 4 * j][1 + tx] = kc[j];
+    }
+    if (hr >= 0) {
+      tw_[hr][hc] = hw;
+      tk_[hr][hc] = hk;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      if (rok[j]) {
+        const int a = a0 + ty + 4 * j;
+        const int r = 1 + ty + 4 * j, cc = 1 + tx;
+        const C w0 = wc[j], k0v = kc[j];
+        C qv;
+        if (k > 0) qv = fL * harm(k0v, km[j]) * (w0 - wm[j]);
+        else qv = C(2) * fL * k0v * w0;
+        if (k + 1 < g.nL) qv += fL * harm(k0v, kn[j]) * (w0 - wn[j]);
+        else qv += C(2) * fL * k0v * w0;
+        if (ORTHO) {
+          const int64_t ii = (int64_t)k * g.plane + col[j];
+          const C kac = (C)ka[ii], kbc = (C)kb[ii];
+          if (a > 0) qv += fa * harm(kac, (C)ka[ii - g.nb]) * (w0 - tw_[r - 1][cc]);
+          if (a + 1 < g.na) qv += fa * harm(kac, (C)ka[ii + g.nb]) * (w0 - tw_[r + 1][cc]);
+          if (b > 0) qv += fb * harm(kbc, (C)kb[ii - 1]) * (w0 - tw_[r][cc - 1]);
+          if (b + 1 < g.nb) qv += fb * harm(kbc, (C)kb[ii + 1]) * (w0 - tw_[r][cc + 1]);
         } else {
-          wn[u] = C(0);
-          kn[u] = C(1);
+          if (a > 0) qv += fa * harm(k0v, tk_[r - 1][cc]) * (w0 - tw_[r - 1][cc]);
+          if (a + 1 < g.na) qv += fa * harm(k0v, tk_[r + 1][cc]) * (w0 - tw_[r + 1][cc]);
+          if (b > 0) qv += fb * harm(k0v, tk_[r][cc - 1]) * (w0 - tw_[r][cc - 1]);
+          if (b + 1 < g.nb) qv += fb * harm(k0v, tk_[r][cc + 1]) * (w0 - tw_[r][cc + 1]);
         }
+        const S qs = (S)qv;
+        q[(int64_t)k * g.plane + col[j]] = qs;
+        acc += (double)w0 * (double)qs;
       }
-#pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const int kk = k + u;
-        if (kk < k1) {
-          const int64_t ii = i + (int64_t)u * g.plane;
-          const C wp = wn[u], kpp = kn[u];
-          C qv;
-          if (kk > 0) qv = fL * harm(kc, km) * (wc - wm);
-          else qv = C(2) * fL * kc * wc;
-          if (kk + 1 < g.nL) qv += fL * harm(kc, kpp) * (wc - wp);
-          else qv += C(2) * fL * kc * wc;
-          const C kac = ORTHO ? (C)ka[ii] : kc, kbc = ORTHO ? (C)kb[ii] : kc;
-          if (has_am) qv += fa * harm(kac, (C)ka[ii - g.nb]) * (wc - (C)w[ii - g.nb]);
-          if (has_ap) qv += fa * harm(kac, (C)ka[ii + g.nb]) * (wc - (C)w[ii + g.nb]);
-          if (has_bm) qv += fb * harm(kbc, (C)kb[ii - 1]) * (wc - (C)w[ii - 1]);
-          if (has_bp) qv += fb * harm(kbc, (C)kb[ii + 1]) * (wc - (C)w[ii + 1]);
-          const S qs = (S)qv;
-          q[ii] = qs;
-          acc += (double)wc * (double)qs;
-          wm = wc;
-          km = kc;
-          wc = wp;
-          kc = kpp;
-        }
-      }
-      i += (int64_t)KU * g.plane;
     }
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      wm[j] = wc[j];
+      km[j] = kc[j];
+      wc[j] = wn[j];
+      kc[j] = kn[j];
+      wn[j] = wnn[j];
+      kn[j] = knn[j];
+    }
+    hw = hwn;
+    hk = hkn;
   }
   if (partials) {
     const double s = block_sum(acc, red);
@@ -609,7 +662,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
 // Strided axis a, in place.  A block owns `tb` adjacent b columns of one
 // plane k = blockIdx.y: every LDS line is one column (length na).
 template <class S, class T, int DIR>
-__global__ __launch_bounds__(256) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
+__global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
                                               int tb, const DevState* __restrict__ st, int gate) {
   // blockIdx.y = global plane; instances of a batch hold nL planes each
   if (st) st += blockIdx.y / g.nL;
@@ -759,7 +812,7 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
   t += (int64_t)blockIdx.z * g.V;
   if (partials) partials += (int64_t)blockIdx.z * gridDim.x * gridDim.y;
   const double* kr = rm.kref + 5 * blockIdx.z;
-  __shared__ double sh[8][P][TB];  // yF yL m11 mmm m1m ts|c' Dsep|d' x
+  __shared__ double sh[7][P][TB];  // yF yL m11 mmm|d' m1m ts|c' x
   __shared__ double red[16];
   const int tid = threadIdx.x;
   const int l = tid % TB, p = tid / TB;
@@ -832,7 +885,6 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
     sh[3][p][l] = invu_last;
     sh[4][p][l] = prod * invu_last;  // (M^{-1})_{1,len}
     sh[5][p][l] = ts;
-    sh[6][p][l] = has_right ? Dof(endp - 1) : 0.0;
   }
   __syncthreads();
   // separator system (Schur complement, symmetric tridiagonal), one thread per line
@@ -842,31 +894,34 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
 #pragma unroll
     for (int qd = 0; qd < P - 1; ++qd) {
       if (qd < nsep) {
+        // separator qd is the last row of partition qd (never row 0 or nL-1
+        // unless it is, which Dof handles)
+        const double Dsep = Dof((qd + 1) * m - 1);
         const double Lq = (qd > 0) ? -a2 * sh[4][qd][l] : 0.0;
-        const double Bq = sh[6][qd][l] - a2 * (sh[3][qd][l] + sh[2][qd + 1][l]);
+        const double Bq = Dsep - a2 * (sh[3][qd][l] + sh[2][qd + 1][l]);
         const double Uq = (qd + 1 < nsep) ? -a2 * sh[4][qd + 1][l] : 0.0;
         const double rq = sh[5][qd][l] - aoff * sh[1][qd][l] - aoff * sh[0][qd + 1][l];
         const double iden = frcp(Bq - Lq * cprev);
         cprev = Uq * iden;
         dprev = (rq - Lq * dprev) * iden;
-        sh[5][qd][l] = cprev;
-        sh[6][qd][l] = dprev;
+        sh[5][qd][l] = cprev;  // ts of separator qd is consumed
+        sh[3][qd][l] = dprev;  // so is (M^{-1})_{len,len} of partition qd
       }
     }
     double x = 0.0;
 #pragma unroll
     for (int qd = P - 2; qd >= 0; --qd) {
       if (qd < nsep) {
-        x = (qd == nsep - 1) ? sh[6][qd][l] : (sh[6][qd][l] - sh[5][qd][l] * x);
-        sh[7][qd][l] = x;
+        x = (qd == nsep - 1) ? sh[3][qd][l] : (sh[3][qd][l] - sh[5][qd][l] * x);
+        sh[6][qd][l] = x;
       }
     }
   }
   __syncthreads();
   double acc = 0.0;
   if (active) {
-    const double zl = (p > 0) ? sh[7][p - 1][l] : 0.0;
-    const double zr = has_right ? sh[7][p][l] : 0.0;
+    const double zl = (p > 0) ? sh[6][p - 1][l] : 0.0;
+    const double zr = has_right ? sh[6][p][l] : 0.0;
     // re-solve M z = t - a zl e_1 - a zr e_len with the stored LU pivots
     double d = 0.0;
 #pragma unroll
