@@ -134,6 +134,45 @@ def cpu_baseline(kap_np, iters_full: int, slab: int = 128, sample_iters: int = 2
                       f"and to {iters_full} passes"}
 
 
+def ensemble_bench(torch, etc, rvegen, args):
+    """Ensemble of 64 log-normal GRF RVEs of mixed edges {48, 64, 96, 128, 160}
+    (per-RVE variance U[0.5, 2], correlation length U[4, 16], contrast <= 1e3,
+    float32 input), mixed form, load x, rtol 1e-6.  A step solves every RVE
+    (same-size RVEs share a batch plan) and reads back every K_eff."""
+    print("bench: generating the GRF ensemble", file=sys.stderr, flush=True)
+    kaps_np, specs = rvegen.grf_ensemble(args.ensemble)
+    kaps = [torch.as_tensor(k, device="cuda:0") for k in kaps_np]
+    V = sum(k.size for k in kaps_np)
+    form = args.forms.split(",")[0]
+    kw = dict(precision=form, rtol=args.rtol, use_graph=args.graph)
+    for _ in range(args.warmup):
+        etc.solve_ensemble(kaps, 0, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = etc.solve_ensemble(kaps, 0, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    es = 4 if form == "mixed" else 8
+    it_bytes = sum(iteration_bytes_per_voxel(es, form == "mixed", 10) * k.size * it
+                   for k, it in zip(kaps_np, out["iters"]))
+    line = {
+        "metric": "RVE ensemble throughput (64 mixed-size GRF RVEs to rel.res 1e-6)",
+        "value": len(kaps) / dt, "unit": "RVEs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage / f64 dots+tridiagonal+refinement" if form == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"grf_ensemble: {len(kaps)} log-normal GRF RVEs, edges 48/64/96/128/160, "
+                               f"{V / 1e6:.1f} M voxels in total, load x, rtol {args.rtol:g}", "form": form,
+                   "graph": bool(args.graph)},
+        "plans": out["plans"],
+        "iters_min_max": [min(out["iters"]), max(out["iters"])],
+        "all_ok": all(s == "ok" for s in out["status"]),
+        "hbm_gbs": it_bytes / dt / 1e9,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +186,9 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run the plain copy kernel on MIB MiB (5 launches) and exit; the byte counters "
                          "of this run calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--ensemble", type=int, default=0, metavar="COUNT",
+                    help="time the mixed-size GRF ensemble of COUNT RVEs instead (RVEs/s)")
+    ap.add_argument("--graph", action="store_true", help="replay the PCG passes from captured HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note"}))
@@ -166,6 +208,9 @@ def main():
             etc.etc_copy_f64(src, dst)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": n * 8, "copy_calib_bytes_written": n * 8, "launches": 5}))
+        return
+    if args.ensemble:
+        ensemble_bench(torch, etc, rvegen, args)
         return
 
     print(f"bench: generating spheres512 at n={args.n}", file=sys.stderr, flush=True)

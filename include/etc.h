@@ -91,6 +91,10 @@ typedef struct {
   size_t workspace_bytes;
   int want_grad;         /* 1: reserve the adjoint state for etc_grad (8 bytes per voxel) */
   etc_precond precond;   /* default ETC_PC_DCT */
+  int use_graph;         /* 1: etc_solve captures `poll_every` passes in a HIP graph on
+                            first use (per solution buffer and Dirichlet pair) and
+                            replays it; ignored while a kernel timer is set.  The
+                            results equal those of the eager path.  Default 0. */
 } etc_options;
 
 typedef struct {

@@ -15,6 +15,7 @@ setup, solve and K_eff for one call.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 __all__ = [
@@ -58,6 +59,7 @@ class _Options(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("want_grad", ctypes.c_int),
         ("precond", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
     ]
 
 
@@ -163,7 +165,7 @@ def _torch():
 
 
 def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_every=8, kref="mid",
-             kref_user=None, L=None, stream=None, want_grad=False, precond="dct") -> _Options:
+             kref_user=None, L=None, stream=None, want_grad=False, precond="dct", use_graph=False) -> _Options:
     lib = load_library()
     o = _Options()
     lib.etc_options_default(ctypes.byref(o))
@@ -182,6 +184,7 @@ def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_e
     o.stream = stream
     o.want_grad = 1 if want_grad else 0
     o.precond = {"dct": 0, "none": 1}[precond]
+    o.use_graph = 1 if use_graph else 0
     return o
 
 
@@ -235,13 +238,14 @@ class Plan:
 def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
               rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
               kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, source=None,
-              p_in_face=None, p_out_face=None, precond: str = "dct") -> Plan:
+              p_in_face=None, p_out_face=None, precond: str = "dct", use_graph: bool = False) -> Plan:
     """Preparation phase on device data (user layout, load axis ``axis``).
 
     ``kappa`` is one tensor (isotropic) or a sequence of three tensors, the
     conductivity along user axes 0, 1, 2 (orthotropic), float64 or float32.
     ``source`` (float64, kappa's shape), ``p_in_face`` / ``p_out_face``
-    (float64 over the two transverse axes in user order) are optional."""
+    (float64 over the two transverse axes in user order) are optional.
+    ``use_graph`` replays the PCG passes from a captured HIP graph."""
     torch = _torch()
     comps = list(kappa) if isinstance(kappa, (list, tuple)) else [kappa]
     if len(comps) not in (1, 3):
@@ -258,7 +262,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
     dtype = "float64" if k0.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(k0.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad, precond)
+                 want_grad, precond, use_graph)
     n = _dims(k0.shape)
     pr = _Problem()
     keep = list(comps)
@@ -295,7 +299,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
 def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
                     rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
                     kref: str = "mid", kref_user=None, L=None, want_grad: bool = False,
-                    precond: str = "dct") -> Plan:
+                    precond: str = "dct", use_graph: bool = False) -> Plan:
     """Batch of same-size RVEs: ``kappa`` has shape (B, n0, n1, n2)."""
     torch = _torch()
     if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda" or kappa.dim() != 4:
@@ -306,7 +310,7 @@ def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0,
     dtype = "float64" if kappa.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(kappa.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad, precond)
+                 want_grad, precond, use_graph)
     nb = int(kappa.shape[0])
     n = _dims(kappa.shape[1:])
     nbytes = ctypes.c_size_t(0)
@@ -349,6 +353,46 @@ def solve_batch(kappa, axis: int = 0, **kw) -> dict:
     out.update(etc_batch_results(plan))
     out.update(etc_keff_batch(plan))
     plan.close()
+    return out
+
+
+def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_grad: bool = False,
+                   **kw) -> dict:
+    """K_eff of an ensemble of RVEs of mixed sizes.
+
+    RVEs of one shape are stacked into batch plans (at most ``max_batch_voxels``
+    voxels per plan), each solved with per-instance exit tests; results are
+    returned in input order.  With ``want_grad`` the gradients dK/dkappa are
+    returned too (one tensor per RVE)."""
+    torch = _torch()
+    buckets: dict = {}
+    for i, k in enumerate(kappas):
+        if not isinstance(k, torch.Tensor) or k.dim() != 3 or k.device.type != "cuda":
+            raise ValueError("every RVE must be a 3D torch tensor on a GPU device")
+        buckets.setdefault((tuple(k.shape), k.dtype), []).append(i)
+    n = len(kappas)
+    out = {"keff": [None] * n, "k_in": [None] * n, "iters": [None] * n, "status": [None] * n,
+           "relres": [None] * n, "plans": 0}
+    if want_grad:
+        out["grad"] = [None] * n
+    for (shape, _), idx in buckets.items():
+        per = max(1, int(max_batch_voxels) // max(1, math.prod(shape)))
+        for c0 in range(0, len(idx), per):
+            part = idx[c0:c0 + per]
+            batch = torch.stack([kappas[i] for i in part])
+            plan = etc_setup_batch(batch, axis, want_grad=want_grad, **kw)
+            del batch
+            etc_solve(plan)
+            res = etc_batch_results(plan)
+            res.update(etc_keff_batch(plan))
+            g = etc_grad(plan) if want_grad else None
+            plan.close()
+            out["plans"] += 1
+            for j, i in enumerate(part):
+                for key in ("keff", "k_in", "iters", "status", "relres"):
+                    out[key][i] = res[key][j]
+                if want_grad:
+                    out["grad"][i] = g[j]
     return out
 
 

@@ -111,6 +111,15 @@ struct etc_plan {
   bool solved;
   int last_iters;              // max over instances
   int last_status;             // worst over instances
+  // captured passes (use_graph): one graph per (solution buffer, Dirichlet pair)
+  hipStream_t cstream;         // capture/replay stream owned by the plan (or nullptr)
+  struct GraphEntry {
+    double* p;
+    double p_in, p_out;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
   // kernel timer
   int timer_id;
   std::vector<hipEvent_t> ev;
@@ -703,6 +712,7 @@ void etc_options_default(etc_options* o) {
   o->stream = nullptr;
   o->want_grad = 0;
   o->precond = ETC_PC_DCT;
+  o->use_graph = 0;
 }
 
 const char* etc_last_error(void) { return g_err.c_str(); }
@@ -988,6 +998,51 @@ static etc_status pull_state(etc_plan* P) {
   return ETC_OK;
 }
 
+// Graph of `poll_every` passes for the current solution buffer and Dirichlet
+// pair, captured on first use and kept until etc_destroy.  Capture needs a
+// stream other than the null stream: a plan on the null stream captures and
+// replays on a blocking stream of its own, which the null stream orders
+// against implicitly.  `*ls` receives the stream to launch the graph on.
+static etc_status graph_for(etc_plan* P, hipGraphExec_t* out, hipStream_t* ls) {
+  hipStream_t cs = P->stream;
+  if (!cs) {
+    if (!P->cstream) HIPCHK(hipStreamCreate(&P->cstream));
+    cs = P->cstream;
+  }
+  *ls = cs;
+  for (auto& e : P->graphs)
+    if (e.p == P->p && e.p_in == P->g.p_in && e.p_out == P->g.p_out) {
+      *out = e.exec;
+      return ETC_OK;
+    }
+  const hipStream_t saved = P->stream;
+  P->stream = cs;
+  etc_plan::GraphEntry e{P->p, P->g.p_in, P->g.p_out, nullptr, nullptr};
+  etc_status s = ETC_OK;
+  hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (he == hipSuccess) {
+    for (int i = 0; i < P->opt.poll_every && s == ETC_OK; ++i)
+      s = (P->prec == ETC_MIXED) ? Ops<float>::iteration(P) : Ops<double>::iteration(P);
+    hipError_t he2 = hipStreamEndCapture(cs, &e.graph);
+    if (he2 != hipSuccess && s == ETC_OK)
+      s = fail(ETC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he2));
+  } else {
+    s = fail(ETC_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(he));
+  }
+  P->stream = saved;
+  if (s) {
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    return s;
+  }
+  if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(e.graph);
+    return fail(ETC_E_HIP, "hipGraphInstantiate failed");
+  }
+  P->graphs.push_back(e);
+  *out = e.exec;
+  return ETC_OK;
+}
+
 extern "C" {
 
 etc_status etc_setup(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
@@ -1030,14 +1085,24 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
   if (s) return s;
   int enq = 0;
   const int chunk = P->opt.poll_every;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t gstream = nullptr;
+  if (P->opt.use_graph && P->timer_id == 0) {
+    if ((s = graph_for(P, &exec, &gstream))) return s;
+    if (gstream != P->stream) HIPCHK(hipStreamSynchronize(P->stream));
+  }
   for (;;) {
     if ((s = pull_state(P))) return s;
     bool all_done = true;
     for (int i = 0; i < P->nseg; ++i) all_done = all_done && P->st_host[i].done;
     if (all_done || enq > P->opt.max_iter) break;
-    for (int i = 0; i < chunk; ++i) {
-      s = (P->prec == ETC_MIXED) ? Ops<float>::iteration(P) : Ops<double>::iteration(P);
-      if (s) return s;
+    if (exec) {
+      HIPCHK(hipGraphLaunch(exec, gstream));
+    } else {
+      for (int i = 0; i < chunk; ++i) {
+        s = (P->prec == ETC_MIXED) ? Ops<float>::iteration(P) : Ops<double>::iteration(P);
+        if (s) return s;
+      }
     }
     enq += chunk;
   }
@@ -1248,6 +1313,14 @@ etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream)
 void etc_destroy(etc_plan* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->stream);
+  for (auto& e : P->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
+  if (P->cstream) {
+    (void)hipStreamSynchronize(P->cstream);
+    (void)hipStreamDestroy(P->cstream);
+  }
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   if (P->own_ws && P->ws) (void)hipFree(P->ws);
   if (P->st_host) (void)hipHostFree(P->st_host);

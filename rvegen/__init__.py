@@ -255,6 +255,29 @@ CONFIGS = {
 }
 
 
+def grf_ensemble_specs(count: int = 64, meta_seed: int = 5, edges=(48, 64, 96, 128, 160),
+                       base_seed: int = 5000):
+    """Specifications of an ensemble of log-normal GRF RVEs of mixed sizes.
+
+    Per RVE ``i``: edge uniform over ``edges``, variance ``sigma2 ~ U[0.5, 2]``,
+    correlation length ``ell ~ U[4, 16]``, field seed ``base_seed + i`` (the
+    draws come from one generator seeded with ``meta_seed``)."""
+    rng = np.random.default_rng(meta_seed)
+    out = []
+    for i in range(count):
+        n = int(edges[int(rng.integers(len(edges)))])
+        sigma2 = float(rng.uniform(0.5, 2.0))
+        ell = float(rng.uniform(4.0, 16.0))
+        out.append(dict(index=i, n=n, sigma2=sigma2, ell=ell, seed=base_seed + i))
+    return out
+
+
+def grf_ensemble(count: int = 64, meta_seed: int = 5, edges=(48, 64, 96, 128, 160), dtype=np.float32):
+    """The conductivity arrays of :func:`grf_ensemble_specs` (contrast <= 1e3)."""
+    specs = grf_ensemble_specs(count, meta_seed, edges)
+    return [grf_lognormal(s["n"], s["sigma2"], s["ell"], s["seed"], 1e3, dtype) for s in specs], specs
+
+
 def make_config(name: str, n: int | None = None):
     """Build the conductivity array of a named workload (optionally at another edge ``n``)."""
     cfg = CONFIGS[name]

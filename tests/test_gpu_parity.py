@@ -412,3 +412,62 @@ def test_batch_solution_and_gradient_layout():
         assert np.abs(p[i] - O.decanonical(ref["pcg"].p, 2)).max() < 1e-9
         gref = O.decanonical(O.keff_gradient(ref["problem"], ref["pcg"].p), 2)
         assert np.abs(g[i] - gref).max() < 1e-8 * np.abs(gref).max()
+
+
+# ------------------------------------------------------------- HIP graphs
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(precision):
+    """use_graph replays captured passes: every solve of a plan (the graph is
+    captured once and replayed many times, with eager work and host
+    synchronisation between the replays) gives the eager path's iterates bit
+    for bit, and the adjoint solve captures a graph of its own."""
+    kap = lognormal((26, 30, 44), seed=77, sigma=1.2)
+    rtol = 1e-10 if precision == "fp64" else 1e-6
+    eager = etc.etc_setup(dev(kap), 0, rtol=rtol, precision=precision, want_grad=True)
+    e_out = etc.etc_solve(eager)
+    e_p = etc.etc_get_solution(eager).cpu().numpy()
+    e_k = etc.etc_keff(eager)["keff"]
+    e_g = etc.etc_grad(eager).cpu().numpy()
+    eager.close()
+    plan = etc.etc_setup(dev(kap), 0, rtol=rtol, precision=precision, want_grad=True, use_graph=True)
+    for rep in range(3):
+        out = etc.etc_solve(plan)
+        assert out["iters"] == e_out["iters"] and out["status"] == "ok", rep
+        assert np.array_equal(etc.etc_get_solution(plan).cpu().numpy(), e_p), rep
+        assert etc.etc_keff(plan)["keff"] == e_k, rep
+        assert np.array_equal(etc.etc_grad(plan).cpu().numpy(), e_g), rep
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_graph_batch_and_side_stream():
+    """Graph replay on a caller's side stream and on a batch plan."""
+    n = 20
+    kaps = np.stack([lognormal((n, n, n), seed=90 + i, sigma=0.3 + 0.4 * i) for i in range(3)])
+    ref = etc.solve_batch(dev(kaps), 1, rtol=1e-9)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = etc.solve_batch(dev(kaps), 1, rtol=1e-9, use_graph=True)
+    torch.cuda.synchronize()
+    assert out["iters"] == ref["iters"]
+    assert out["keff"] == ref["keff"]
+
+
+# --------------------------------------------------------------- ensembles
+def test_ensemble_of_mixed_sizes_matches_oracle():
+    """solve_ensemble buckets RVEs by shape into batch plans (split when a
+    bucket exceeds the voxel cap) and returns results in input order; each
+    K_eff equals the oracle's, gradients included."""
+    edges = [12, 16, 12, 20, 16, 12]
+    kaps_np = [rvegen.grf_lognormal(n, 1.0 + 0.2 * i, 4.0, 600 + i, dtype=np.float64) for i, n in enumerate(edges)]
+    out = etc.solve_ensemble([dev(k) for k in kaps_np], 1, max_batch_voxels=2 * 12 ** 3, rtol=1e-11,
+                             want_grad=True)
+    assert out["plans"] == 4   # 12^3 bucket of three split in two
+    for i, k in enumerate(kaps_np):
+        ref = O.solve(k, 1, rtol=1e-13)
+        assert out["status"][i] == "ok"
+        assert abs(out["keff"][i] - ref["keff"]) <= 1e-9 * ref["keff"], i
+        gref = O.decanonical(O.keff_gradient(ref["problem"], ref["pcg"].p), 1)
+        g = out["grad"][i].cpu().numpy()
+        assert g.shape == k.shape
+        assert np.abs(g - gref).max() <= 1e-7 * np.abs(gref).max(), i
