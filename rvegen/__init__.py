@@ -199,7 +199,7 @@ def grf_lognormal(n: int, sigma2: float = 1.0, ell: float = 8.0, seed: int = 3,
     spec = 8.0 * np.pi * sigma2 * ell ** 3 / (1.0 + kk * ell * ell) ** 2
     f *= np.sqrt(spec)
     del kk, spec
-    g = np.fft.irfftn(f, s=(m, m, m))[:n, :n, :n]
+    g = np.fft.irfftn(f, s=(m, m, m), axes=(0, 1, 2))[:n, :n, :n]
     del f
     g = (g - g.mean()) / g.std() * math.sqrt(sigma2)
     half = 0.5 * math.log(clip_contrast)

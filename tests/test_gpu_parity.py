@@ -462,7 +462,8 @@ def test_ensemble_of_mixed_sizes_matches_oracle():
     kaps_np = [rvegen.grf_lognormal(n, 1.0 + 0.2 * i, 4.0, 600 + i, dtype=np.float64) for i, n in enumerate(edges)]
     out = etc.solve_ensemble([dev(k) for k in kaps_np], 1, max_batch_voxels=2 * 12 ** 3, rtol=1e-11,
                              want_grad=True)
-    assert out["plans"] == 4   # 12^3 bucket of three split in two
+    # cap of two 12^3 RVEs: 12^3 x3 -> 2 plans, 16^3 x2 -> 2 plans, 20^3 -> 1 plan
+    assert out["plans"] == 5
     for i, k in enumerate(kaps_np):
         ref = O.solve(k, 1, rtol=1e-13)
         assert out["status"][i] == "ok"
