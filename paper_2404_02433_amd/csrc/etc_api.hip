@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "etc.h"
@@ -132,6 +133,27 @@ namespace {
 
 size_t elt_size(etc_precision prec) { return prec == ETC_MIXED ? sizeof(float) : sizeof(double); }
 
+// Transform lengths with compile-time DCT kernels (the benchmark edge and the
+// ensemble edges); any other length runs the run-time-shaped kernels.
+template <class T, bool ROWS, class F>
+bool ct_dispatch(int, int, F&) {
+  return false;
+}
+template <class T, bool ROWS, class F, int N0, int... Ns>
+bool ct_dispatch(int N, int shape, F& f) {
+  if (N == N0 && shape == (ROWS ? DctShape<T, N0>::rows : DctShape<T, N0>::cols)) {
+    f(std::integral_constant<int, N0>{});
+    return true;
+  }
+  return ct_dispatch<T, ROWS, F, Ns...>(N, shape, f);
+}
+// Calls f(std::integral_constant<int, NC>) with NC = N if N has compile-time
+// kernels whose lines (columns) per block equal `shape`, else with NC = 0.
+template <class T, bool ROWS, class F>
+void with_ct_len(int N, int shape, F&& f) {
+  if (!ct_dispatch<T, ROWS, F, 512, 256, 128, 64, 160, 96, 48>(N, shape, f)) f(std::integral_constant<int, 0>{});
+}
+
 // Factor M into the radices of the LDS FFT; false if a prime factor > 5 remains.
 bool factor_radices(int M, DctPlan& dp) {
   dp.nst = 0;
@@ -154,9 +176,7 @@ DctPlan make_dct_plan(int N) {
   dp.fft = 0;
   if (N >= 2 && N % 2 == 0 && factor_radices(N / 2, dp)) dp.fft = 1;
   if (dp.fft) {
-    int ls = (dp.M - 1) + ((dp.M - 1) >> 4) + 1;
-    if (ls % 2 == 0) ls += 1;
-    dp.lstride = ls;  // complex slots per line
+    dp.lstride = fft_lstride(dp.M);  // complex slots per line
   } else {
     dp.nst = 0;
     dp.lstride = (N + 1) / 2 + 1;  // complex slots holding N reals
@@ -202,12 +222,11 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     lc.gridR = dim3(gx, gy4, nch4 * ns);
     lc.nR = gx * gy4 * nch4;
   }
-  // rows (b axis)
+  // rows (b axis); the same shape rules as the compile-time kernels
+  static_assert(kThreads == 256, "row kernels are shaped for 256 threads");
   {
     const size_t line_bytes = (size_t)dpb.lstride * cx_sz;
-    int rpb = (int)std::max<size_t>(1, (48 * 1024) / line_bytes);
-    if (dpb.fft) rpb = std::min(rpb, std::max(1, 16 * kThreads / dpb.M));
-    rpb = std::min(rpb, 64);
+    int rpb = rows_lines(dpb.M, dpb.lstride, (int)elt, dpb.fft != 0);
     lc.nrows = g.nL * g.na;
     rpb = std::min(rpb, lc.nrows);
     lc.rpb = rpb;
@@ -215,17 +234,12 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     lc.gridRows = dim3(lc.nRows, ns);
     lc.ldsRows = (size_t)rpb * line_bytes;
   }
-  // columns (a axis)
+  // columns (a axis); float32 columns use 512-thread blocks so 32-wide tiles
+  // (128-byte rows) still fit one pass per FFT stage
   {
     const size_t line_bytes = (size_t)dpa.lstride * cx_sz;
-    int tb = (int)std::max<size_t>(1, (80 * 1024) / line_bytes);
-    // float32 columns use 512-thread blocks so 32-wide tiles (128-byte rows)
-    // still fit one pass per FFT stage (16 complex values per thread)
-    lc.colThreads = (elt == 4) ? 2 * kThreads : kThreads;
-    if (dpa.fft) tb = std::min(tb, std::max(1, 16 * lc.colThreads / dpa.M));
-    tb = std::min(tb, 32);
-    if (tb >= 16) tb = 16 * (tb / 16);
-    else if (tb >= 8) tb = 8;
+    lc.colThreads = cols_threads((int)elt);
+    int tb = cols_tile(dpa.M, dpa.lstride, (int)elt, dpa.fft != 0);
     tb = std::min(tb, g.nb);
     lc.tb = tb;
     lc.gridCols = dim3((g.nb + tb - 1) / tb, g.nL * ns, 1);
@@ -430,20 +444,70 @@ template <class S> struct Ops {
     return ETC_OK;
   }
 
-  // Dynamic LDS above 64 KiB must be requested per kernel (gfx950 has 160 KiB per CU).
+  // Dynamic LDS above 64 KiB must be requested per kernel (gfx950 has 160 KiB
+  // per CU): the run-time-shaped kernels and the compile-time ones of this length.
   static etc_status lds_limits(etc_plan* P) {
     const int cols = (int)P->lc.ldsCols, rows = (int)P->lc.ldsRows;
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* fn, int bytes) {
+      if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    };
     if (cols > 65536) {
-      HIPCHK(hipFuncSetAttribute((const void*)&k_cols<S, T, -1>, hipFuncAttributeMaxDynamicSharedMemorySize, cols));
-      HIPCHK(hipFuncSetAttribute((const void*)&k_cols<S, T, +1>, hipFuncAttributeMaxDynamicSharedMemorySize, cols));
+      auto f = [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        set((const void*)&k_cols<S, T, -1, NC>, cols);
+        set((const void*)&k_cols<S, T, +1, NC>, cols);
+      };
+      f(std::integral_constant<int, 0>{});
+      with_ct_len<T, false>(P->dpa.N, P->lc.tb, f);
     }
     if (rows > 65536) {
-      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_fwd<S, T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
-      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_fwd<S, T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
-      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_inv<S, T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
-      HIPCHK(hipFuncSetAttribute((const void*)&k_rows_inv<S, T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, rows));
+      auto f = [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        set((const void*)&k_rows_fwd<S, T, 0, NC>, rows);
+        set((const void*)&k_rows_fwd<S, T, 1, NC>, rows);
+        set((const void*)&k_rows_inv<S, T, 0, NC>, rows);
+        set((const void*)&k_rows_inv<S, T, 1, NC>, rows);
+      };
+      f(std::integral_constant<int, 0>{});
+      with_ct_len<T, true>(P->dpb.N, P->lc.rpb, f);
     }
+    if (e != hipSuccess) return fail(ETC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     return ETC_OK;
+  }
+
+  // DCT launches: compile-time kernels for the common lengths, else the
+  // run-time-shaped ones.
+  template <int MODE>
+  static void rows_fwd(etc_plan* P, const S* src, S* dst, S* x, const S* w, S* r, const S* q, double* partials,
+                       const DevState* st, int gate) {
+    const LaunchCfg& lc = P->lc;
+    const cx<T>* twb = (const cx<T>*)P->tw_b;
+    with_ct_len<T, true>(P->dpb.N, lc.rpb, [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      k_rows_fwd<S, T, MODE, NC><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
+          P->g, P->dpb, twb, src, dst, lc.rpb, lc.nrows, x, w, r, q, partials, st, gate);
+    });
+  }
+  template <int MODE>
+  static void rows_inv(etc_plan* P, const S* src, S* dst, const DevState* st, int gate) {
+    const LaunchCfg& lc = P->lc;
+    const cx<T>* twb = (const cx<T>*)P->tw_b;
+    with_ct_len<T, true>(P->dpb.N, lc.rpb, [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      k_rows_inv<S, T, MODE, NC><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, src, dst,
+                                                                                 lc.rpb, lc.nrows, st, gate);
+    });
+  }
+  template <int DIR>
+  static void cols(etc_plan* P, S* t, const DevState* st, int gate) {
+    const LaunchCfg& lc = P->lc;
+    const cx<T>* twa = (const cx<T>*)P->tw_a;
+    with_ct_len<T, false>(P->dpa.N, lc.tb, [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      k_cols<S, T, DIR, NC><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st,
+                                                                                  gate);
+    });
   }
 
   static RefMedium ref(const etc_plan* P) {
@@ -493,25 +557,18 @@ template <class S> struct Ops {
                             int fin_op) {
     const LaunchCfg& lc = P->lc;
     S* t = (S*)P->t;
-    const cx<T>* twa = (const cx<T>*)P->tw_a;
-    const cx<T>* twb = (const cx<T>*)P->tw_b;
-    k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
-        P->g, P->dpb, twb, src, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, st, gate);
+    rows_fwd<0>(P, src, t, nullptr, nullptr, nullptr, nullptr, nullptr, st, gate);
     LAUNCHCHK("rows_fwd");
-    k_cols<S, T, -1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
+    cols<-1>(P, t, st, gate);
     LAUNCHCHK("cols_fwd");
     etc_status s = thomas(P, t, P->partials, st, gate);
     if (s) return s;
     s = fin(P, fin_op, lc.nThomas, lc.nThomas);
     if (s) return s;
-    k_cols<S, T, +1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st, gate);
+    cols<+1>(P, t, st, gate);
     LAUNCHCHK("cols_inv");
-    if (inv_mode == 1)
-      k_rows_inv<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, t, dst, lc.rpb,
-                                                                           lc.nrows, st, gate);
-    else
-      k_rows_inv<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, t, dst, lc.rpb,
-                                                                           lc.nrows, st, gate);
+    if (inv_mode == 1) rows_inv<1>(P, t, dst, st, gate);
+    else rows_inv<0>(P, t, dst, st, gate);
     LAUNCHCHK("rows_inv");
     return ETC_OK;
   }
@@ -588,13 +645,10 @@ template <class S> struct Ops {
   static etc_status iteration(etc_plan* P) {
     if (P->opt.precond == ETC_PC_NONE) return iteration_plain(P);
     const LaunchCfg& lc = P->lc;
-    const Geo& g = P->g;
     S* r = (S*)P->r;
     S* w = (S*)P->w;
     S* q = (S*)P->q;
     S* t = (S*)P->t;
-    const cx<T>* twa = (const cx<T>*)P->tw_a;
-    const cx<T>* twb = (const cx<T>*)P->tw_b;
     etc_status s;
     // q = A w, alpha = rho / (w . q)
     timer_begin(P, 1);
@@ -604,9 +658,7 @@ template <class S> struct Ops {
     if ((s = fin(P, FIN_ALPHA, lc.nA, lc.nA))) return s;
     // x += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
     timer_begin(P, 2);
-    k_rows_fwd<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(g, P->dpb, twb, nullptr, t, lc.rpb,
-                                                                         lc.nrows, xsol(P), w, r, q, P->partials,
-                                                                         P->st, 1);
+    rows_fwd<1>(P, nullptr, t, xsol(P), w, r, q, P->partials, P->st, 1);
     timer_end(P, 2);
     LAUNCHCHK("update_rows_fwd");
     if ((s = fin(P, FIN_RR, lc.nRows, lc.nRows))) return s;
@@ -616,12 +668,11 @@ template <class S> struct Ops {
       if ((s = flush(P))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
       if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
-      k_rows_fwd<S, T, 0><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
-          g, P->dpb, twb, r, t, lc.rpb, lc.nrows, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
+      rows_fwd<0>(P, r, t, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
       LAUNCHCHK("rows_fwd_refine");
     }
     timer_begin(P, 3);
-    k_cols<S, T, -1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
+    cols<-1>(P, t, P->st, 1);
     timer_end(P, 3);
     LAUNCHCHK("cols_fwd");
     timer_begin(P, 4);
@@ -630,13 +681,12 @@ template <class S> struct Ops {
     if (s) return s;
     if ((s = fin(P, FIN_BETA, lc.nThomas, lc.nThomas))) return s;
     timer_begin(P, 5);
-    k_cols<S, T, +1><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(g, P->dpa, twa, t, lc.tb, P->st, 1);
+    cols<+1>(P, t, P->st, 1);
     timer_end(P, 5);
     LAUNCHCHK("cols_inv");
     // w = DCT_b^{-1}(t) + beta w
     timer_begin(P, 6);
-    k_rows_inv<S, T, 1><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(g, P->dpb, twb, t, w, lc.rpb, lc.nrows,
-                                                                         P->st, 1);
+    rows_inv<1>(P, t, w, P->st, 1);
     timer_end(P, 6);
     LAUNCHCHK("rows_inv_dir");
     return ETC_OK;

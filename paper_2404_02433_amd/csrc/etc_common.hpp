@@ -75,6 +75,17 @@ __device__ __forceinline__ int flat_block() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
+// Work-groups are dealt to the 8 XCDs round-robin by flat id.  Renumber so
+// that each XCD receives one contiguous range of tiles: tiles that share halo
+// lines then run on the same XCD at about the same time and meet in its L2.
+// A bijection of [0, total) for any total.
+__device__ __forceinline__ int xcd_tile(int id, int total) {
+  constexpr int NX = 8;
+  const int x = id % NX, j = id / NX;
+  const int per = total / NX, rem = total % NX;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
+}
+
 template <class T> __device__ __forceinline__ double to_d(T v) { return static_cast<double>(v); }
 
 // Harmonic-mean face conductivity 2 k1 k2 / (k1 + k2) of two cells.

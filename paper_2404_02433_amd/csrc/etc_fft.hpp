@@ -227,6 +227,125 @@ __device__ void lds_fft(cx<T>* buf, int lines, int ls, const DctPlan& dp, const 
   }
 }
 
+// ------------------------------------------------ compile-time specialisation
+// For the common lengths the whole stage schedule is fixed at compile time:
+// line count, line stride, radices and stage strides are constants, so every
+// index split (line, butterfly, twiddle) is a shift or a constant multiply.
+// The launch shapes below are shared with the host so that both sides agree.
+struct RadixPlan {
+  int n;  // number of stages, -1 if M has a prime factor > 5
+  int r[8];
+};
+
+__host__ __device__ constexpr RadixPlan radix_plan(int M) {
+  RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = M;
+  const int pref[6] = {16, 8, 4, 2, 3, 5};
+  for (int i = 0; i < 6; ++i)
+    while (m % pref[i] == 0 && m >= pref[i]) {
+      if (p.n >= 8) return RadixPlan{-1, {0, 0, 0, 0, 0, 0, 0, 0}};
+      p.r[p.n++] = pref[i];
+      m /= pref[i];
+    }
+  if (m != 1) p.n = -1;
+  return p;
+}
+
+// LDS slots (complex) per line of M complex values: padded, odd.
+__host__ __device__ constexpr int fft_lstride(int M) {
+  const int ls = (M - 1) + ((M - 1) >> 4) + 1;
+  return (ls % 2 == 0) ? ls + 1 : ls;
+}
+
+// Lines per block of the row transforms (256 threads): an LDS budget of
+// 48 KiB and at most 16 complex values per thread and stage.
+__host__ __device__ constexpr int rows_lines(int M, int ls, int elt, bool fft) {
+  const int line_bytes = ls * 2 * elt;
+  int r = (48 * 1024) / line_bytes;
+  if (r < 1) r = 1;
+  if (fft) {
+    int c = 16 * 256 / M;
+    if (c < 1) c = 1;
+    if (c < r) r = c;
+  }
+  return r < 64 ? r : 64;
+}
+
+// Columns per block of the column transforms (256 threads in float64, 512 in
+// float32): an LDS budget of 80 KiB, at most 16 complex values per thread and
+// stage, 16 or 32 columns when they fit (whole 128-byte rows).
+__host__ __device__ constexpr int cols_threads(int elt) { return elt == 4 ? 512 : 256; }
+__host__ __device__ constexpr int cols_tile(int M, int ls, int elt, bool fft) {
+  const int line_bytes = ls * 2 * elt;
+  int tb = (80 * 1024) / line_bytes;
+  if (tb < 1) tb = 1;
+  if (fft) {
+    int c = 16 * cols_threads(elt) / M;
+    if (c < 1) c = 1;
+    if (c < tb) tb = c;
+  }
+  if (tb > 32) tb = 32;
+  if (tb >= 16) tb = 16 * (tb / 16);
+  else if (tb >= 8) tb = 8;
+  return tb;
+}
+
+// One radix-R Stockham stage over LINES lines of M points (line stride LS),
+// all shapes compile-time.  Same data flow as fft_stage.
+template <class T, int R, int DIR, int M, int NS, int LINES, int NTHR, int LS>
+__device__ __attribute__((noinline)) void fft_stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+  constexpr int per_line = M / R;
+  constexpr int items = LINES * per_line;
+  constexpr int step = M / (NS * R);
+  constexpr int IPT = (items + NTHR - 1) / NTHR;
+  cx<T> v[IPT][R];
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int it = tid + i * NTHR;
+    if (items % NTHR == 0 || it < items) {
+      const int line = it / per_line, j = it - line * per_line;
+      const cx<T>* L = buf + line * LS;
+      const int jm = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = L[lpad(j + r * per_line)];
+      if (NS > 1 && jm != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[8 * step * r * jm];
+          if (DIR > 0) w.im = -w.im;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dftR<R, DIR>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int it = tid + i * NTHR;
+    if (items % NTHR == 0 || it < items) {
+      const int line = it / per_line, j = it - line * per_line;
+      cx<T>* L = buf + line * LS;
+      const int jm = j % NS;
+      const int idxD = (j / NS) * NS * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) L[lpad(idxD + r * NS)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <class T, int DIR, int M, int LINES, int NTHR, int LS, int S = 0, int NS = 1>
+__device__ __forceinline__ void lds_fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+  constexpr RadixPlan rp = radix_plan(M);
+  static_assert(rp.n > 0, "length not supported by the compile-time route");
+  if constexpr (S < rp.n) {
+    constexpr int R = rp.r[S];
+    fft_stage_ct<T, R, DIR, M, NS, LINES, NTHR, LS>(buf, tw, tid);
+    lds_fft_ct<T, DIR, M, LINES, NTHR, LS, S + 1, NS * R>(buf, tw, tid);
+  }
+}
+
 // Position of input sample j in the reordered sequence v (FFT route).
 __device__ __forceinline__ int dct_perm(int j, int N) { return (j & 1) ? (N - 1 - (j >> 1)) : (j >> 1); }
 

@@ -249,9 +249,14 @@ template <class S, class C, bool ORTHO>
 __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w, Kap<S> kp, S* __restrict__ q,
                                                  double* __restrict__ partials, const DevState* __restrict__ st,
                                                  int gate, int kchunk) {
-  // blockIdx.z = instance * chunks + chunk (instances of a batch are V apart)
+  // tile (bx, by, bz), bz = instance * chunks + chunk (instances of a batch
+  // are V apart), renumbered so that neighbouring tiles share an XCD; the
+  // partial sums are stored by tile so that each instance's are contiguous
+  const int ntile = gridDim.x * gridDim.y * gridDim.z;
+  const int tile = xcd_tile(flat_block(), ntile);
+  const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
   const int nch = (g.nL + kchunk - 1) / kchunk;
-  const int inst = blockIdx.z / nch, chunk = blockIdx.z - inst * nch;
+  const int inst = bz / nch, chunk = bz - inst * nch;
   if (st) st += inst;
   if (gated_out(st, gate)) return;
   {
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
   __shared__ C tk_[ATA + 2][ATB + 2];
   __shared__ double red[16];
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int b0 = blockIdx.x * ATB, a0 = blockIdx.y * ATA;
+  const int b0 = bx * ATB, a0 = by * ATA;
   const int b = b0 + tx;
   const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
@@ -372,18 +377,22 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
   }
   if (partials) {
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0 && threadIdx.y == 0) partials[flat_block()] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[tile] = s;
   }
 }
 
 // r = b - A p in double arithmetic (p double, kappa at its input precision),
-// stored at S precision, with the partial ||r||^2.  Same tiling as k_apply_A.
+// stored at S precision, with the partial ||r||^2.  Columns of 64 b x 4 a
+// march along k; lateral neighbours come through the caches (tiles
+// renumbered per XCD as in k_apply_A).
 template <class S, bool ORTHO>
 __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restrict__ p, Kap<S> kp, Rhs rh,
                                                   S* __restrict__ r, double* __restrict__ partials,
                                                   const DevState* __restrict__ st, int gate, int kchunk) {
+  const int tile = xcd_tile(flat_block(), gridDim.x * gridDim.y * gridDim.z);
+  const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
   const int nch = (g.nL + kchunk - 1) / kchunk;
-  const int inst = blockIdx.z / nch, chunk = blockIdx.z - inst * nch;
+  const int inst = bz / nch, chunk = bz - inst * nch;
   if (st) st += inst;
   if (gated_out(st, gate)) return;
   {
@@ -394,8 +403,8 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
     if (rh.src) rh.src += off;
   }
   __shared__ double red[16];
-  const int b = blockIdx.x * 64 + threadIdx.x;
-  const int a = blockIdx.y * 4 + threadIdx.y;
+  const int b = bx * 64 + threadIdx.x;
+  const int a = by * 4 + threadIdx.y;
   const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
   const bool valid = (a < g.na) && (b < g.nb);
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
     }
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[flat_block()] = s;
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[tile] = s;
 }
 
 // ============================================================ DCT along rows
@@ -450,17 +459,41 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
 // stores, so every wave keeps several HBM requests in flight.
 constexpr int UNR = 8;
 
+// Compile-time shape of the DCT kernels: NC = 0 takes every length and
+// launch shape from the plan at run time; NC > 0 fixes the transform length
+// (even, FFT route) and with it the line stride and lines per block.
+template <class T, int NC> struct DctShape {
+  static constexpr bool ct = NC > 0;
+  static constexpr int M = NC / 2;
+  static constexpr int ls = ct ? fft_lstride(M) : 0;
+  static constexpr int rows = ct ? rows_lines(M, ls, (int)sizeof(T), true) : 0;
+  static constexpr int cols = ct ? cols_tile(M, ls, (int)sizeof(T), true) : 0;
+  static constexpr int col_threads = cols_threads((int)sizeof(T));
+  // loads per thread that cover a whole block in one batch (all in flight)
+  static constexpr int row_elems = ct ? (rows * NC + 255) / 256 : 0;
+  static constexpr int row_items = ct ? (rows * (M / 2 + 1) + 255) / 256 : 0;
+  static constexpr int col_elems = ct ? (cols * NC + col_threads - 1) / col_threads : 0;
+  static constexpr int col_items = ct ? (cols * (M / 2 + 1) + col_threads - 1) / col_threads : 0;
+};
+
+// Unroll of a load batch: the whole block when the shape is compile-time
+// (capped by a register budget of `cap` values per thread), else `dflt`.
+__host__ __device__ constexpr int batch_of(int whole, int cap, int dflt) {
+  return whole > 0 ? (whole < cap ? whole : cap) : dflt;
+}
+
 // Rows are the contiguous b lines; a block owns `rpb` whole rows.
 // MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): x += alpha w,
 // r -= alpha q, partial ||r||^2, t = DCT_b(r).  x is the solution p in the
 // FP64 form and the float32 increment since the last refinement in the
 // mixed form (flushed into the float64 p by k_flush).
-template <class S, class T, int MODE>
+template <class S, class T, int MODE, int NC = 0>
 __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
                                                   S* __restrict__ p, const S* __restrict__ w, S* __restrict__ r,
                                                   const S* __restrict__ q, double* __restrict__ partials,
                                                   const DevState* __restrict__ st, int gate) {
+  using Sh = DctShape<T, NC>;
   // instance blockIdx.y of a batch
   if (st) st += blockIdx.y;
   if (gated_out(st, gate)) return;
@@ -479,38 +512,44 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   __shared__ double red[16];
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int N = dp.N;
-  const int64_t row0 = (int64_t)blockIdx.x * rpb;
-  const int lines = (int)min((int64_t)rpb, (int64_t)nrows - row0);
+  const int tid = threadIdx.x;
+  constexpr int nthr = 256;
+  const int N = Sh::ct ? NC : dp.N;
+  const int M = Sh::ct ? Sh::M : dp.M;
+  const bool fft = Sh::ct ? true : (dp.fft != 0);
+  const int ls = Sh::ct ? Sh::ls : dp.lstride;
+  const int rpbv = Sh::ct ? Sh::rows : rpb;
+  const int64_t row0 = (int64_t)blockIdx.x * rpbv;
+  const int lines = (int)min((int64_t)rpbv, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
   const int total = lines * N;
   double acc = 0.0;
   double alpha = 0.0;
   if (MODE == 1) alpha = st->alpha;
-  const int ls = dp.lstride;
-  // load (and update) the rows into LDS, reordered for the FFT route
-  constexpr int U = (MODE == 1) ? 4 : UNR;
+  // load (and update) the rows into LDS, reordered for the FFT route; each
+  // batch issues all its loads before the first use (64 registers of values)
+  constexpr int U = (MODE == 1) ? batch_of(Sh::row_elems, 64 / (2 * (int)sizeof(S)), 4)
+                                : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
   for (int e0 = tid; e0 < total; e0 += nthr * U) {
     T x[U];
     if (MODE == 1) {
-      double pv[U], wv[U], rv[U], qv[U];
+      S pv[U], wv[U], rv[U], qv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
-          pv[u] = (double)p[base + e];
-          wv[u] = (double)w[base + e];
-          rv[u] = (double)r[base + e];
-          qv[u] = (double)q[base + e];
+          pv[u] = p[base + e];
+          wv[u] = w[base + e];
+          rv[u] = r[base + e];
+          qv[u] = q[base + e];
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
-          p[base + e] = (S)(pv[u] + alpha * wv[u]);
-          const S rs = (S)(rv[u] - alpha * qv[u]);
+          p[base + e] = (S)((double)pv[u] + alpha * (double)wv[u]);
+          const S rs = (S)((double)rv[u] - alpha * (double)qv[u]);
           r[base + e] = rs;
           acc += (double)rs * (double)rs;
           x[u] = (T)rs;
@@ -529,15 +568,16 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
       if (e < total) {
         const int line = e / N, j = e - line * N;
         T* L = reinterpret_cast<T*>(buf + line * ls);
-        if (dp.fft) L[vpos(dct_perm(j, N))] = x[u];
+        if (fft) L[vpos(dct_perm(j, N))] = x[u];
         else L[j] = x[u];
       }
     }
   }
   __syncthreads();
-  if (dp.fft) {
-    lds_fft<T, -1>(buf, lines, ls, dp, tw, tid, nthr);
-    const int M = dp.M, nit = M / 2 + 1;
+  if (fft) {
+    if constexpr (Sh::ct) lds_fft_ct<T, -1, Sh::M, Sh::rows, nthr, Sh::ls>(buf, tw, tid);
+    else lds_fft<T, -1>(buf, lines, ls, dp, tw, tid, nthr);
+    const int nit = M / 2 + 1;
     for (int e = tid; e < lines * nit; e += nthr) {
       const int line = e / nit, k = e - line * nit;
       S* out = dst + base + (int64_t)line * N;
@@ -561,10 +601,11 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
 
 // Inverse along rows.  MODE 0: dst = DCT_b^{-1}(src).  MODE 1: dst holds w on
 // entry and leaves with w = z + beta w, z = DCT_b^{-1}(src) (never stored).
-template <class S, class T, int MODE>
+template <class S, class T, int MODE, int NC = 0>
 __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
                                                   const DevState* __restrict__ st, int gate) {
+  using Sh = DctShape<T, NC>;
   if (st) st += blockIdx.y;
   if (gated_out(st, gate)) return;
   {
@@ -574,19 +615,23 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int N = dp.N;
-  const int64_t row0 = (int64_t)blockIdx.x * rpb;
-  const int lines = (int)min((int64_t)rpb, (int64_t)nrows - row0);
+  const int tid = threadIdx.x;
+  constexpr int nthr = 256;
+  const int N = Sh::ct ? NC : dp.N;
+  const int M = Sh::ct ? Sh::M : dp.M;
+  const bool fft = Sh::ct ? true : (dp.fft != 0);
+  const int ls = Sh::ct ? Sh::ls : dp.lstride;
+  const int rpbv = Sh::ct ? Sh::rows : rpb;
+  const int64_t row0 = (int64_t)blockIdx.x * rpbv;
+  const int lines = (int)min((int64_t)rpbv, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
   const int total = lines * N;
-  const int ls = dp.lstride;
   double beta = 0.0;
   if (MODE == 1) beta = st->beta;
-  if (dp.fft) {
-    const int M = dp.M, nit = M / 2 + 1;
+  if (fft) {
+    const int nit = M / 2 + 1;
     const int items = lines * nit;
-    constexpr int UI = 4;
+    constexpr int UI = batch_of(Sh::row_items, 64 / (4 * ((int)sizeof(S) / 4)), 4);
     for (int e0 = tid; e0 < items; e0 += nthr * UI) {
       T xv[UI][4];
 #pragma unroll
@@ -613,25 +658,27 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
       }
     }
     __syncthreads();
-    lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
+    if constexpr (Sh::ct) lds_fft_ct<T, +1, Sh::M, Sh::rows, nthr, Sh::ls>(buf, tw, tid);
+    else lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
     const T invM = T(1) / T(M);
-    for (int e0 = tid; e0 < total; e0 += nthr * UNR) {
-      double wv[UNR];
+    constexpr int UO = batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
+    for (int e0 = tid; e0 < total; e0 += nthr * UO) {
+      S wv[UO];
       if (MODE == 1) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
+        for (int u = 0; u < UO; ++u) {
           const int e = e0 + u * nthr;
-          if (e < total) wv[u] = (double)dst[base + e];
+          if (e < total) wv[u] = dst[base + e];
         }
       }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
+      for (int u = 0; u < UO; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
           const int line = e / N, j = e - line * N;
           const T* L = reinterpret_cast<const T*>(buf + line * ls);
           const T z = L[vpos(dct_perm(j, N))] * invM;
-          if (MODE == 1) dst[base + e] = (S)((double)z + beta * wv[u]);
+          if (MODE == 1) dst[base + e] = (S)((double)z + beta * (double)wv[u]);
           else dst[base + e] = (S)z;
         }
       }
@@ -660,56 +707,65 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
 
 // ========================================================= DCT along columns
 // Strided axis a, in place.  A block owns `tb` adjacent b columns of one
-// plane k = blockIdx.y: every LDS line is one column (length na).
-template <class S, class T, int DIR>
+// plane k = blockIdx.y: every LDS line is one column (length na).  Element e
+// of a block is (row n, column c) = (e / tb, e % tb); columns beyond the
+// right edge of the plane are skipped.
+template <class S, class T, int DIR, int NC = 0>
 __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
                                               int tb, const DevState* __restrict__ st, int gate) {
+  using Sh = DctShape<T, NC>;
   // blockIdx.y = global plane; instances of a batch hold nL planes each
   if (st) st += blockIdx.y / g.nL;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int N = dp.N;  // = na
-  const int b0 = blockIdx.x * tb;
-  const int lines = min(tb, g.nb - b0);
+  const int tid = threadIdx.x;
+  const int nthr = Sh::ct ? Sh::col_threads : (int)blockDim.x;
+  const int N = Sh::ct ? NC : dp.N;  // = na
+  const int M = Sh::ct ? Sh::M : dp.M;
+  const bool fft = Sh::ct ? true : (dp.fft != 0);
+  const int ls = Sh::ct ? Sh::ls : dp.lstride;
+  const int tbv = Sh::ct ? Sh::cols : tb;
+  const int b0 = blockIdx.x * tbv;
+  const int lines = min(tbv, g.nb - b0);
   S* pl = data + (int64_t)blockIdx.y * g.plane + b0;
-  const int ls = dp.lstride;
-  const int total = lines * N;
+  const int total = tbv * N;
   if (DIR < 0) {
-    for (int e0 = tid; e0 < total; e0 += nthr * UNR) {
-      T x[UNR];
+    constexpr int UC = batch_of(Sh::col_elems, 64 / ((int)sizeof(S) / 4), UNR);
+    for (int e0 = tid; e0 < total; e0 += nthr * UC) {
+      S x[UC];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
+      for (int u = 0; u < UC; ++u) {
         const int e = e0 + u * nthr;
-        if (e < total) {
-          const int n = e / lines, c = e - n * lines;
-          x[u] = (T)pl[(int64_t)n * g.nb + c];
-        }
+        const int n = e / tbv, c = e - n * tbv;
+        if (e < total && c < lines) x[u] = pl[(int64_t)n * g.nb + c];
       }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
+      for (int u = 0; u < UC; ++u) {
         const int e = e0 + u * nthr;
-        if (e < total) {
-          const int n = e / lines, c = e - n * lines;
+        const int n = e / tbv, c = e - n * tbv;
+        if (e < total && c < lines) {
           T* L = reinterpret_cast<T*>(buf + c * ls);
-          if (dp.fft) L[vpos(dct_perm(n, N))] = x[u];
-          else L[n] = x[u];
+          if (fft) L[vpos(dct_perm(n, N))] = (T)x[u];
+          else L[n] = (T)x[u];
         }
       }
     }
     __syncthreads();
-    if (dp.fft) {
-      lds_fft<T, -1>(buf, lines, ls, dp, tw, tid, nthr);
-      const int M = dp.M, nit = M / 2 + 1;
-      for (int e = tid; e < lines * nit; e += nthr) {
-        const int k = e / lines, c = e - k * lines;
-        dct_post(buf + c * ls, k, N, M, tw, [&](int idx, T v) { pl[(int64_t)idx * g.nb + c] = (S)v; });
+    if (fft) {
+      if constexpr (Sh::ct) lds_fft_ct<T, -1, Sh::M, Sh::cols, Sh::col_threads, Sh::ls>(buf, tw, tid);
+      else lds_fft<T, -1>(buf, lines, ls, dp, tw, tid, nthr);
+      const int nit = M / 2 + 1;
+      for (int e = tid; e < tbv * nit; e += nthr) {
+        const int k = e / tbv, c = e - k * tbv;
+        if (c < lines)
+          dct_post(buf + c * ls, k, N, M, tw, [&](int idx, T v) { pl[(int64_t)idx * g.nb + c] = (S)v; });
       }
     } else {
       const int N4 = 4 * N;
       for (int e = tid; e < total; e += nthr) {
-        const int k = e / lines, c = e - k * lines;
+        const int k = e / tbv, c = e - k * tbv;
+        if (c >= lines) continue;
         const T* L = reinterpret_cast<const T*>(buf + c * ls);
         T s = T(0);
         for (int n = 0; n < N; ++n) s += L[n] * tw[((2 * n + 1) * k) % N4].re;
@@ -717,17 +773,17 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
       }
     }
   } else {
-    if (dp.fft) {
-      const int M = dp.M, nit = M / 2 + 1;
-      const int items = lines * nit;
-      constexpr int UI = 4;
+    if (fft) {
+      const int nit = M / 2 + 1;
+      const int items = tbv * nit;
+      constexpr int UI = batch_of(Sh::col_items, 64 / (4 * ((int)sizeof(S) / 4)), 4);
       for (int e0 = tid; e0 < items; e0 += nthr * UI) {
         T xv[UI][4];
 #pragma unroll
         for (int u = 0; u < UI; ++u) {
           const int e = e0 + u * nthr;
-          if (e < items) {
-            const int k = e / lines, c = e - k * lines;
+          const int k = e / tbv, c = e - k * tbv;
+          if (e < items && c < lines) {
             int i0, i1, i2, i3;
             pre_inv_idx(k, N, M, i0, i1, i2, i3);
             xv[u][0] = (T)pl[(int64_t)i0 * g.nb + c];
@@ -739,23 +795,25 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
 #pragma unroll
         for (int u = 0; u < UI; ++u) {
           const int e = e0 + u * nthr;
-          if (e < items) {
-            const int k = e / lines, c = e - k * lines;
+          const int k = e / tbv, c = e - k * tbv;
+          if (e < items && c < lines)
             dct_pre_inv_vals(buf + c * ls, k, M, tw, xv[u][0], xv[u][1], xv[u][2], xv[u][3]);
-          }
         }
       }
       __syncthreads();
-      lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
+      if constexpr (Sh::ct) lds_fft_ct<T, +1, Sh::M, Sh::cols, Sh::col_threads, Sh::ls>(buf, tw, tid);
+      else lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
       const T invM = T(1) / T(M);
       for (int e = tid; e < total; e += nthr) {
-        const int n = e / lines, c = e - n * lines;
+        const int n = e / tbv, c = e - n * tbv;
+        if (c >= lines) continue;
         const T* L = reinterpret_cast<const T*>(buf + c * ls);
         pl[(int64_t)n * g.nb + c] = (S)(L[vpos(dct_perm(n, N))] * invM);
       }
     } else {
       for (int e = tid; e < total; e += nthr) {
-        const int n = e / lines, c = e - n * lines;
+        const int n = e / tbv, c = e - n * tbv;
+        if (c >= lines) continue;
         T* L = reinterpret_cast<T*>(buf + c * ls);
         L[n] = (T)pl[(int64_t)n * g.nb + c];
       }
@@ -763,7 +821,8 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
       const int N4 = 4 * N;
       const T sc = T(2) / T(N);
       for (int e = tid; e < total; e += nthr) {
-        const int n = e / lines, c = e - n * lines;
+        const int n = e / tbv, c = e - n * tbv;
+        if (c >= lines) continue;
         const T* L = reinterpret_cast<const T*>(buf + c * ls);
         T s = T(0.5) * L[0];
         for (int k = 1; k < N; ++k) s += L[k] * tw[((2 * n + 1) * k) % N4].re;
@@ -791,13 +850,15 @@ __device__ __forceinline__ double frcp(double u) {
 // Partitioned elimination keeps every value in registers: the block holds TB
 // adjacent modes (lines, coalesced) times P partitions of each line.  A
 // partition is `len` interior rows followed by one separator row (none for
-// the last partition).  Phase 1: each thread loads its rows, runs the LU
-// sweep of its interior block M (pivots kept) and the UL sweep as a scalar
-// chain, giving y = M^{-1} t at both ends and the corner entries of M^{-1}.
-// The separators then form a symmetric tridiagonal Schur complement, solved
-// by one thread per line.  Phase 2: each thread moves its two separator
-// couplings to the right-hand side and re-solves its block with the stored
-// pivots.
+// the last partition).  Phase 1: each thread loads its rows and runs the LU
+// sweep of its interior block M = L D L^T (pivots kept).  The same sweep
+// gives both ends of y = M^{-1} t and the corner entries of M^{-1}: with
+// g = L^{-1} e_1 (a running product of the multipliers), y_1 = sum_j g_j d_j,
+// (M^{-1})_{11} = sum_j g_j^2 / u_j, (M^{-1})_{1,len} = g_len / u_len.  The
+// separators then form a symmetric tridiagonal Schur complement, solved by
+// parallel cyclic reduction with one thread per separator.  Phase 2: each
+// thread moves its two separator couplings to the right-hand side and
+// re-solves its block with the stored pivots.
 //
 // Also returns the partial of r . z: by the DCT's Parseval relation it equals
 // (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r;
@@ -812,7 +873,7 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
   t += (int64_t)blockIdx.z * g.V;
   if (partials) partials += (int64_t)blockIdx.z * gridDim.x * gridDim.y;
   const double* kr = rm.kref + 5 * blockIdx.z;
-  __shared__ double sh[7][P][TB];  // yF yL m11 mmm|d' m1m ts|c' x
+  __shared__ double sh[6][P][TB];  // phase 1: yF yL m11 mLL m1L ts; reduction: L U r 1/B; x
   __shared__ double red[16];
   const int tid = threadIdx.x;
   const int l = tid % TB, p = tid / TB;
@@ -837,15 +898,15 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
   const int64_t col = (int64_t)am * g.nb + bm;
   // register arrays are only ever indexed by unrolled constants
   double tv[MAXM], invu[MAXM];
-  double quad = 0.0, ts = 0.0, invu_last = 0.0, y_last = 0.0, y_first = 0.0, m11 = 0.0, prod = 1.0;
+  double quad = 0.0, ts = 0.0, y_last = 0.0, y_first = 0.0, m11 = 0.0, gj = 1.0;
   if (active) {
 #pragma unroll
     for (int j = 0; j < MAXM; ++j)
       if (j < len) tv[j] = (double)t[(int64_t)(start + j) * g.plane + col];
     if (has_right) ts = (double)t[(int64_t)(endp - 1) * g.plane + col];
-    // LU sweep: pivots u_j (kept as 1/u_j), d'_j as a scalar chain,
-    // t^T M^{-1} t = sum_j d'_j f_j, (M^{-1})_{1,len} = prod_j (-c'_j) / u_last
-    double dprev = 0.0;
+    // LU sweep: pivots u_j (kept as 1/u_j), d_j = (L D)^{-1} t as a scalar
+    // chain; t^T M^{-1} t = sum_j d_j f_j with f = L^{-1} t
+    double dprev = 0.0, iu = 0.0;
 #pragma unroll
     for (int j = 0; j < MAXM; ++j) {
       if (j < len) {
@@ -854,74 +915,79 @@ __global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __rest
           u = Dof(start);
           f = tv[0];
         } else {
-          u = Dof(start + j) - a2 * invu[j - 1];
+          u = Dof(start + j) - a2 * iu;
           f = tv[j] - aoff * dprev;
-          prod *= -(aoff * invu[j - 1]);
+          gj *= -(aoff * iu);
         }
-        invu[j] = frcp(u);
-        dprev = f * invu[j];
+        iu = frcp(u);
+        invu[j] = iu;
+        dprev = f * iu;
         quad += dprev * f;
-        if (j == len - 1) invu_last = invu[j];
+        y_first += gj * dprev;
+        m11 += gj * gj * iu;
       }
     }
     y_last = dprev;
-    // UL sweep (bottom-up) as a scalar chain: y_0 and (M^{-1})_{11}
-    double iv = 0.0, gch = 0.0;
-#pragma unroll
-    for (int j = MAXM - 1; j >= 0; --j) {
-      if (j < len) {
-        const bool bottom = (j == len - 1);
-        const double v = Dof(start + j) - (bottom ? 0.0 : a2 * iv);
-        const double ivn = frcp(v);
-        gch = (tv[j] - (bottom ? 0.0 : aoff * gch)) * ivn;
-        iv = ivn;
-      }
-    }
-    y_first = gch;
-    m11 = iv;
     sh[0][p][l] = y_first;
     sh[1][p][l] = y_last;
     sh[2][p][l] = m11;
-    sh[3][p][l] = invu_last;
-    sh[4][p][l] = prod * invu_last;  // (M^{-1})_{1,len}
+    sh[3][p][l] = iu;       // (M^{-1})_{len,len}
+    sh[4][p][l] = gj * iu;  // (M^{-1})_{1,len}
     sh[5][p][l] = ts;
   }
   __syncthreads();
-  // separator system (Schur complement, symmetric tridiagonal), one thread per line
-  if (p == 0 && line_ok && Peff > 1) {
-    const int nsep = Peff - 1;
-    double cprev = 0.0, dprev = 0.0;
-#pragma unroll
-    for (int qd = 0; qd < P - 1; ++qd) {
-      if (qd < nsep) {
-        // separator qd is the last row of partition qd (never row 0 or nL-1
-        // unless it is, which Dof handles)
-        const double Dsep = Dof((qd + 1) * m - 1);
-        const double Lq = (qd > 0) ? -a2 * sh[4][qd][l] : 0.0;
-        const double Bq = Dsep - a2 * (sh[3][qd][l] + sh[2][qd + 1][l]);
-        const double Uq = (qd + 1 < nsep) ? -a2 * sh[4][qd + 1][l] : 0.0;
-        const double rq = sh[5][qd][l] - aoff * sh[1][qd][l] - aoff * sh[0][qd + 1][l];
-        const double iden = frcp(Bq - Lq * cprev);
-        cprev = Uq * iden;
-        dprev = (rq - Lq * dprev) * iden;
-        sh[5][qd][l] = cprev;  // ts of separator qd is consumed
-        sh[3][qd][l] = dprev;  // so is (M^{-1})_{len,len} of partition qd
-      }
+  // Separator q (the last row of partition q) couples to q - 1 and q + 1:
+  // L_q x_{q-1} + B_q x_q + U_q x_{q+1} = r_q.  Parallel cyclic reduction:
+  // at stride h every row eliminates its neighbours q - h and q + h, so after
+  // ceil(log2 nsep) steps each row stands alone.
+  const int nsep = Peff - 1;
+  const int q = p;
+  const bool sep = line_ok && q < nsep;
+  double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
+  if (sep) {
+    const double Dsep = Dof((q + 1) * m - 1);
+    Lq = (q > 0) ? -a2 * sh[4][q][l] : 0.0;
+    Bq = Dsep - a2 * (sh[3][q][l] + sh[2][q + 1][l]);
+    Uq = (q + 1 < nsep) ? -a2 * sh[4][q + 1][l] : 0.0;
+    rq = sh[5][q][l] - aoff * sh[1][q][l] - aoff * sh[0][q + 1][l];
+  }
+  for (int h = 1; h < nsep; h <<= 1) {
+    __syncthreads();  // every read of the previous contents is done
+    const double iB = frcp(Bq);
+    if (sep) {
+      sh[0][q][l] = Lq;
+      sh[1][q][l] = Uq;
+      sh[2][q][l] = rq;
+      sh[3][q][l] = iB;
     }
-    double x = 0.0;
-#pragma unroll
-    for (int qd = P - 2; qd >= 0; --qd) {
-      if (qd < nsep) {
-        x = (qd == nsep - 1) ? sh[3][qd][l] : (sh[3][qd][l] - sh[5][qd][l] * x);
-        sh[6][qd][l] = x;
+    __syncthreads();
+    if (sep) {
+      double nL_ = 0.0, nU = 0.0, nB = Bq, nr = rq;
+      if (q - h >= 0) {
+        const double al = -Lq * sh[3][q - h][l];
+        nL_ = al * sh[0][q - h][l];
+        nB += al * sh[1][q - h][l];
+        nr += al * sh[2][q - h][l];
       }
+      if (q + h < nsep) {
+        const double ga = -Uq * sh[3][q + h][l];
+        nU = ga * sh[1][q + h][l];
+        nB += ga * sh[0][q + h][l];
+        nr += ga * sh[2][q + h][l];
+      }
+      Lq = nL_;
+      Uq = nU;
+      Bq = nB;
+      rq = nr;
     }
   }
   __syncthreads();
+  if (sep) sh[5][q][l] = rq / Bq;  // separator value x_q
+  __syncthreads();
   double acc = 0.0;
   if (active) {
-    const double zl = (p > 0) ? sh[6][p - 1][l] : 0.0;
-    const double zr = has_right ? sh[6][p][l] : 0.0;
+    const double zl = (p > 0) ? sh[5][p - 1][l] : 0.0;
+    const double zr = has_right ? sh[5][p][l] : 0.0;
     // re-solve M z = t - a zl e_1 - a zr e_len with the stored LU pivots
     double d = 0.0;
 #pragma unroll
