@@ -62,8 +62,8 @@ struct LaunchCfg {
   dim3 gridCols;
   size_t ldsCols;
   // tridiagonal
-  dim3 gridThomas;
-  int Puse, maxm, nThomas;
+  dim3 gridThomas;  // persistent blocks per instance (x) times instances (z)
+  int Puse, maxm, nThomas, thomasTiles;
   // grid-stride kernels
   dim3 gridStride;
   int nStride;
@@ -252,8 +252,9 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
     lc.Puse = Puse;
     lc.maxm = m;
     const int tbm = elt == 4 ? kThomasTBf : kThomasTB;
-    lc.gridThomas = dim3((g.nb + tbm - 1) / tbm, g.na, ns);
-    lc.nThomas = lc.gridThomas.x * lc.gridThomas.y;
+    lc.thomasTiles = (g.nb + tbm - 1) / tbm;
+    lc.nThomas = lc.thomasTiles * g.na;  // tiles (and partial sums) per instance
+    lc.gridThomas = dim3(lc.nThomas, 1, ns);  // capped to the resident blocks at setup
   }
   int64_t gs = (g.V + kThreads - 1) / kThreads;
   lc.nStride = (int)std::min<int64_t>(gs, std::max<int64_t>(8, kMaxGridStride / ns));
@@ -518,17 +519,54 @@ template <class S> struct Ops {
     return rm;
   }
 
+  // Tridiagonal kernel of this plan's shape: exact partitions (nL = 32 m)
+  // for the common lengths, else the guarded variant with room for m rows.
+  template <class F>
+  static void with_thomas(const LaunchCfg& lc, int nL, F&& f) {
+    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
+    constexpr int PP = kThomasP;
+    const bool exact = lc.Puse == PP && nL == PP * lc.maxm;
+    if (exact && lc.maxm == 16) f(&k_thomas<S, TB, PP, 16, true>);
+    else if (exact && lc.maxm == 8) f(&k_thomas<S, TB, PP, 8, true>);
+    else if (exact && lc.maxm == 5) f(&k_thomas<S, TB, PP, 5, true>);
+    else if (exact && lc.maxm == 4) f(&k_thomas<S, TB, PP, 4, true>);
+    else if (exact && lc.maxm == 3) f(&k_thomas<S, TB, PP, 3, true>);
+    else if (exact && lc.maxm == 2) f(&k_thomas<S, TB, PP, 2, true>);
+    else if (lc.maxm <= 4) f(&k_thomas<S, TB, PP, 4, false>);
+    else if (lc.maxm <= 8) f(&k_thomas<S, TB, PP, 8, false>);
+    else if (lc.maxm <= 16) f(&k_thomas<S, TB, PP, 16, false>);
+    else if (lc.maxm <= 32) f(&k_thomas<S, TB, PP, 32, false>);
+    else f(&k_thomas<S, TB, PP, 64, false>);
+  }
+
+  // Persistent grid of the tridiagonal kernel: the blocks that fit on the device at once.
+  static etc_status thomas_grid(etc_plan* P) {
+    LaunchCfg& lc = P->lc;
+    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
+    int dev = 0, cus = 0, occ = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    hipError_t e = hipSuccess;
+    with_thomas(lc, P->g.nL, [&](auto fn) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, TB * kThomasP, 0);
+    });
+    if (e != hipSuccess) return fail(ETC_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    const int ns = P->nseg;
+    const int resident = std::max(1, cus * std::max(1, occ));
+    const int per = std::max(1, std::min(lc.nThomas, (resident + ns - 1) / ns));
+    lc.gridThomas = dim3(per, 1, ns);
+    return ETC_OK;
+  }
+
   static etc_status thomas(etc_plan* P, S* t, double* partials, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     const RefMedium rm = ref(P);
     constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
     const int threads = TB * kThomasP;
-    if (lc.maxm <= 16)
-      k_thomas<S, TB, kThomasP, 16><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
-    else if (lc.maxm <= 32)
-      k_thomas<S, TB, kThomasP, 32><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
-    else
-      k_thomas<S, TB, kThomasP, 64><<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate);
+    with_thomas(lc, P->g.nL, [&](auto fn) {
+      fn<<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate, lc.thomasTiles,
+                                                   lc.nThomas);
+    });
     LAUNCHCHK("thomas");
     return ETC_OK;
   }
@@ -931,6 +969,8 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
   };
 
   s = (P->prec == ETC_MIXED) ? Ops<float>::lds_limits(P) : Ops<double>::lds_limits(P);
+  if (s) return bail(s);
+  s = (P->prec == ETC_MIXED) ? Ops<float>::thomas_grid(P) : Ops<double>::thomas_grid(P);
   if (s) return bail(s);
   if (ps.faces) {
     // face data: [a][b] over the transverse axes in user order (constant pair where NULL)

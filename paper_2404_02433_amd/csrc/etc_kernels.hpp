@@ -863,163 +863,218 @@ __device__ __forceinline__ double frcp(double u) {
 // Also returns the partial of r . z: by the DCT's Parseval relation it equals
 // (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r;
 // per block, t . z = t^T M^{-1} t + (coupling) * (ends of M^{-1} t).
-template <class S, int TB, int P, int MAXM>
-__global__ __launch_bounds__(TB* P) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
+//
+// Blocks are persistent: block x of instance z handles tiles x, x + gridDim.x,
+// ... (a tile is TB modes b' of one mode a').  PF: the block loads the next
+// tile's rows into registers before it works on the current one, so HBM
+// traffic overlaps the elimination (float32 rows; float64 rows would cost
+// the registers of a second block per CU, which hides latency better).
+// EXACT: nL = P * MAXM (every partition has MAXM rows), which removes the
+// ragged-length guards.
+template <class S, int TB, int P, int MAXM, bool EXACT, bool PF = ((EXACT && sizeof(S) == 4) || MAXM <= 8)>
+__global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
-                                                  int gate) {
+                                                  int gate, int ntx, int ntiles) {
   // instance blockIdx.z of a batch
   if (st) st += blockIdx.z;
   if (gated_out(st, gate)) return;
   t += (int64_t)blockIdx.z * g.V;
-  if (partials) partials += (int64_t)blockIdx.z * gridDim.x * gridDim.y;
+  if (partials) partials += (int64_t)blockIdx.z * ntiles;
   const double* kr = rm.kref + 5 * blockIdx.z;
   __shared__ double sh[6][P][TB];  // phase 1: yF yL m11 mLL m1L ts; reduction: L U r 1/B; x
   __shared__ double red[16];
   const int tid = threadIdx.x;
   const int l = tid % TB, p = tid / TB;
-  const int bm = blockIdx.x * TB + l;  // mode b'
-  const int am = blockIdx.y;           // mode a'
   const int nL = g.nL;
-  const int m = (nL + Puse - 1) / Puse;
-  const int Peff = (nL + m - 1) / m;
-  const bool line_ok = bm < g.nb;
+  const int m = EXACT ? MAXM : (nL + Puse - 1) / Puse;
+  const int Peff = EXACT ? P : (nL + m - 1) / m;
   const int start = p * m;
-  const bool active = line_ok && p < Peff;
-  const bool has_right = active && (p < Peff - 1);
+  const bool pok = p < Peff;
+  const bool right = pok && (p < Peff - 1);  // partition ends in a separator row
   const int endp = min(start + m, nL);
-  const int len = active ? (endp - start - (has_right ? 1 : 0)) : 0;
+  const int lenp = pok ? (endp - start - (right ? 1 : 0)) : 0;
   const double kL = kr[0];
-  const double s = line_ok ? (rm.lam_a[am] * kr[1] + rm.lam_b[bm] * kr[2]) : 0.0;
   const double aoff = -kL;
   const double a2 = kL * kL;
-  const double Dint = s + 2.0 * kL, D0 = s + kL + 2.0 * kr[3], DN = s + kL + 2.0 * kr[4];
-  auto Dof = [&](int k) { return k == 0 ? D0 : (k == nL - 1 ? DN : Dint); };
-
-  const int64_t col = (int64_t)am * g.nb + bm;
-  // register arrays are only ever indexed by unrolled constants
-  double tv[MAXM], invu[MAXM];
-  double quad = 0.0, ts = 0.0, y_last = 0.0, y_first = 0.0, m11 = 0.0, gj = 1.0;
-  if (active) {
-#pragma unroll
-    for (int j = 0; j < MAXM; ++j)
-      if (j < len) tv[j] = (double)t[(int64_t)(start + j) * g.plane + col];
-    if (has_right) ts = (double)t[(int64_t)(endp - 1) * g.plane + col];
-    // LU sweep: pivots u_j (kept as 1/u_j), d_j = (L D)^{-1} t as a scalar
-    // chain; t^T M^{-1} t = sum_j d_j f_j with f = L^{-1} t
-    double dprev = 0.0, iu = 0.0;
-#pragma unroll
-    for (int j = 0; j < MAXM; ++j) {
-      if (j < len) {
-        double u, f;
-        if (j == 0) {
-          u = Dof(start);
-          f = tv[0];
-        } else {
-          u = Dof(start + j) - a2 * iu;
-          f = tv[j] - aoff * dprev;
-          gj *= -(aoff * iu);
-        }
-        iu = frcp(u);
-        invu[j] = iu;
-        dprev = f * iu;
-        quad += dprev * f;
-        y_first += gj * dprev;
-        m11 += gj * gj * iu;
-      }
-    }
-    y_last = dprev;
-    sh[0][p][l] = y_first;
-    sh[1][p][l] = y_last;
-    sh[2][p][l] = m11;
-    sh[3][p][l] = iu;       // (M^{-1})_{len,len}
-    sh[4][p][l] = gj * iu;  // (M^{-1})_{1,len}
-    sh[5][p][l] = ts;
-  }
-  __syncthreads();
-  // Separator q (the last row of partition q) couples to q - 1 and q + 1:
-  // L_q x_{q-1} + B_q x_q + U_q x_{q+1} = r_q.  Parallel cyclic reduction:
-  // at stride h every row eliminates its neighbours q - h and q + h, so after
-  // ceil(log2 nsep) steps each row stands alone.
+  const double Dint0 = 2.0 * kL;
+  // extra diagonal of the first row of the line (k = 0) and of the last (k = nL - 1)
+  const double dfirst = (start == 0) ? (kr[3] * 2.0 - kL) : 0.0;
+  const double dlast = (pok && !right) ? (kr[4] * 2.0 - kL) : 0.0;
+  const int64_t plane = g.plane;
   const int nsep = Peff - 1;
   const int q = p;
-  const bool sep = line_ok && q < nsep;
-  double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
-  if (sep) {
-    const double Dsep = Dof((q + 1) * m - 1);
-    Lq = (q > 0) ? -a2 * sh[4][q][l] : 0.0;
-    Bq = Dsep - a2 * (sh[3][q][l] + sh[2][q + 1][l]);
-    Uq = (q + 1 < nsep) ? -a2 * sh[4][q + 1][l] : 0.0;
-    rq = sh[5][q][l] - aoff * sh[1][q][l] - aoff * sh[0][q + 1][l];
-  }
-  for (int h = 1; h < nsep; h <<= 1) {
-    __syncthreads();  // every read of the previous contents is done
-    const double iB = frcp(Bq);
-    if (sep) {
-      sh[0][q][l] = Lq;
-      sh[1][q][l] = Uq;
-      sh[2][q][l] = rq;
-      sh[3][q][l] = iB;
+
+  auto row_ok = [&](int j) { return EXACT ? (j < MAXM - 1 || !right) : (j < lenp); };
+  auto load = [&](int tile, S* v, S& vs) {
+    const int bm = (tile % ntx) * TB + l, am = tile / ntx;
+    if (pok && bm < g.nb) {
+      const S* src = t + (int64_t)start * plane + (int64_t)am * g.nb + bm;
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j)
+        if (row_ok(j)) v[j] = src[(int64_t)j * plane];
+      if (right) vs = src[(int64_t)(endp - 1 - start) * plane];
+    }
+  };
+
+  // PF: the next tile's rows are prefetched into registers (when they fit)
+  S cur[MAXM], cur_s = S(0);
+  int tile = blockIdx.x;
+  if (PF && tile < ntiles) load(tile, cur, cur_s);
+  for (; tile < ntiles; tile += gridDim.x) {
+    S nxt[PF ? MAXM : 1], nxt_s = S(0);
+    const int tn = tile + gridDim.x;
+    if (PF) {
+      if (tn < ntiles) load(tn, nxt, nxt_s);
+    } else {
+      load(tile, cur, cur_s);
+    }
+
+    const int bm = (tile % ntx) * TB + l, am = tile / ntx;
+    const bool line_ok = bm < g.nb;
+    const bool active = line_ok && pok;
+    const bool has_right = active && right;
+    const int len = active ? lenp : 0;
+    const double sft = line_ok ? (rm.lam_a[am] * kr[1] + rm.lam_b[bm] * kr[2]) : 0.0;
+    const double Dint = sft + Dint0;
+    // register arrays are only ever indexed by unrolled constants
+    double dv[MAXM], invu[MAXM];
+    double quad = 0.0, ts = 0.0, y_last = 0.0, y_first = 0.0, m11 = 0.0, gj = 1.0;
+    if (active) {
+      ts = (double)cur_s;
+      // LU sweep of the partition block M = L D L^T: pivots u_j (kept as
+      // 1/u_j), d_j = (L D)^{-1} t, t^T M^{-1} t = sum d_j f_j (f = L^{-1} t)
+      double dprev = 0.0, iu = 0.0;
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) {
+        if (EXACT || j < len) {
+          if (!EXACT || j < MAXM - 1 || !has_right) {
+            double u = Dint;
+            double f = (double)cur[j];
+            if (j == 0) {
+              u += dfirst;
+            } else {
+              u -= a2 * iu;
+              f -= aoff * dprev;
+              gj *= -(aoff * iu);
+            }
+            if (j == (EXACT ? MAXM - 1 : len - 1)) u += dlast;
+            iu = frcp(u);
+            invu[j] = iu;
+            dprev = f * iu;
+            quad += dprev * f;
+            y_first += gj * dprev;
+            m11 += gj * gj * iu;
+          }
+        }
+      }
+      y_last = dprev;
+      sh[0][p][l] = y_first;
+      sh[1][p][l] = y_last;
+      sh[2][p][l] = m11;
+      sh[3][p][l] = iu;       // (M^{-1})_{len,len}
+      sh[4][p][l] = gj * iu;  // (M^{-1})_{1,len}
+      sh[5][p][l] = ts;
     }
     __syncthreads();
+    // Separator q (the last row of partition q) couples to q - 1 and q + 1:
+    // L_q x_{q-1} + B_q x_q + U_q x_{q+1} = r_q.  Parallel cyclic reduction:
+    // at stride h every row eliminates its neighbours q - h and q + h, so
+    // after ceil(log2 nsep) steps each row stands alone.
+    const bool sep = line_ok && q < nsep;
+    double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
     if (sep) {
-      double nL_ = 0.0, nU = 0.0, nB = Bq, nr = rq;
-      if (q - h >= 0) {
-        const double al = -Lq * sh[3][q - h][l];
-        nL_ = al * sh[0][q - h][l];
-        nB += al * sh[1][q - h][l];
-        nr += al * sh[2][q - h][l];
-      }
-      if (q + h < nsep) {
-        const double ga = -Uq * sh[3][q + h][l];
-        nU = ga * sh[1][q + h][l];
-        nB += ga * sh[0][q + h][l];
-        nr += ga * sh[2][q + h][l];
-      }
-      Lq = nL_;
-      Uq = nU;
-      Bq = nB;
-      rq = nr;
+      // the separator is an interior row (never k = 0 or nL - 1)
+      Lq = (q > 0) ? -a2 * sh[4][q][l] : 0.0;
+      Bq = Dint - a2 * (sh[3][q][l] + sh[2][q + 1][l]);
+      Uq = (q + 1 < nsep) ? -a2 * sh[4][q + 1][l] : 0.0;
+      rq = sh[5][q][l] - aoff * sh[1][q][l] - aoff * sh[0][q + 1][l];
     }
-  }
-  __syncthreads();
-  if (sep) sh[5][q][l] = rq / Bq;  // separator value x_q
-  __syncthreads();
-  double acc = 0.0;
-  if (active) {
-    const double zl = (p > 0) ? sh[5][p - 1][l] : 0.0;
-    const double zr = has_right ? sh[5][p][l] : 0.0;
-    // re-solve M z = t - a zl e_1 - a zr e_len with the stored LU pivots
-    double d = 0.0;
-#pragma unroll
-    for (int j = 0; j < MAXM; ++j) {
-      if (j < len) {
-        double f = tv[j];
-        if (j == 0) f -= aoff * zl;
-        else f -= aoff * d;
-        if (j == len - 1) f -= aoff * zr;
-        d = f * invu[j];
-        tv[j] = d;
+    for (int h = 1; h < nsep; h <<= 1) {
+      __syncthreads();  // every read of the previous contents is done
+      const double iB = frcp(Bq);
+      if (sep) {
+        sh[0][q][l] = Lq;
+        sh[1][q][l] = Uq;
+        sh[2][q][l] = rq;
+        sh[3][q][l] = iB;
+      }
+      __syncthreads();
+      if (sep) {
+        double nL_ = 0.0, nU = 0.0, nB = Bq, nr = rq;
+        if (q - h >= 0) {
+          const double al = -Lq * sh[3][q - h][l];
+          nL_ = al * sh[0][q - h][l];
+          nB += al * sh[1][q - h][l];
+          nr += al * sh[2][q - h][l];
+        }
+        if (q + h < nsep) {
+          const double ga = -Uq * sh[3][q + h][l];
+          nU = ga * sh[1][q + h][l];
+          nB += ga * sh[0][q + h][l];
+          nr += ga * sh[2][q + h][l];
+        }
+        Lq = nL_;
+        Uq = nU;
+        Bq = nB;
+        rq = nr;
       }
     }
-    double z = 0.0;
+    __syncthreads();
+    if (sep) sh[5][q][l] = rq / Bq;  // separator value x_q
+    __syncthreads();
+    double acc = 0.0;
+    if (active) {
+      const double zl = (p > 0) ? sh[5][p - 1][l] : 0.0;
+      const double zr = has_right ? sh[5][p][l] : 0.0;
+      const double c1 = -aoff * zl, cm = -aoff * zr;
+      // z = M^{-1} (t + c1 e_1 + cm e_len): forward elimination with the
+      // couplings at both ends, then back substitution, both with the stored
+      // pivots
+      const int lastj = EXACT ? (has_right ? MAXM - 2 : MAXM - 1) : len - 1;
+      double d = 0.0;
 #pragma unroll
-    for (int j = MAXM - 1; j >= 0; --j) {
-      if (j < len) {
-        z = (j == len - 1) ? tv[j] : (tv[j] - aoff * invu[j] * z);
-        tv[j] = z;
+      for (int j = 0; j < MAXM; ++j) {
+        if ((EXACT && (j < MAXM - 1 || !has_right)) || (!EXACT && j < len)) {
+          double f = (double)cur[j];
+          f += (j == 0) ? c1 : -aoff * d;
+          if (j == lastj) f += cm;
+          d = f * invu[j];
+          if constexpr (sizeof(S) == 8) cur[j] = d;  // float64 rows: in place
+          else dv[j] = d;
+        }
       }
-    }
+      double z = 0.0;
 #pragma unroll
-    for (int j = 0; j < MAXM; ++j)
-      if (j < len) t[(int64_t)(start + j) * g.plane + col] = (S)tv[j];
-    if (has_right) t[(int64_t)(endp - 1) * g.plane + col] = (S)zr;
-    const double c1 = -aoff * zl, cm = -aoff * zr;
-    const double wa = (am == 0) ? 0.5 : 1.0, wb = (bm == 0) ? 0.5 : 1.0;
-    acc = wa * wb * (quad + c1 * y_first + cm * y_last + (has_right ? ts * zr : 0.0));
-  }
-  if (partials) {
-    const double sum = block_sum(acc, red);
-    if (tid == 0) partials[blockIdx.x + gridDim.x * blockIdx.y] = sum * (4.0 / ((double)g.na * (double)g.nb));
+      for (int j = MAXM - 1; j >= 0; --j) {
+        if ((EXACT && (j < MAXM - 1 || !has_right)) || (!EXACT && j < len)) {
+          if constexpr (sizeof(S) == 8) {
+            z = (j == lastj) ? (double)cur[j] : ((double)cur[j] - aoff * invu[j] * z);
+            cur[j] = z;
+          } else {
+            z = (j == lastj) ? dv[j] : (dv[j] - aoff * invu[j] * z);
+            dv[j] = z;
+          }
+        }
+      }
+      S* dst = t + (int64_t)start * plane + (int64_t)am * g.nb + bm;
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j)
+        if ((EXACT && (j < MAXM - 1 || !has_right)) || (!EXACT && j < len))
+          dst[(int64_t)j * plane] = (sizeof(S) == 8) ? cur[j] : (S)dv[j];
+      if (has_right) dst[(int64_t)(endp - 1 - start) * plane] = (S)zr;
+      const double wa = (am == 0) ? 0.5 : 1.0, wb = (bm == 0) ? 0.5 : 1.0;
+      acc = wa * wb * (quad + c1 * y_first + cm * y_last + (has_right ? ts * zr : 0.0));
+    }
+    if (partials) {
+      const double sum = block_sum(acc, red);
+      if (tid == 0) partials[tile] = sum * (4.0 / ((double)g.na * (double)g.nb));
+    }
+    __syncthreads();  // the next tile rewrites sh
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) cur[j] = nxt[j];
+      cur_s = nxt_s;
+    }
   }
 }
 
