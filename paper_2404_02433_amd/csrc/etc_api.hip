@@ -756,7 +756,7 @@ template <class S> struct Ops {
     if (P->ortho)
       k_apply_A<S, S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
     else
-      k_apply_A<S, S, false><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
+      k_apply_A_iso<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
     LAUNCHCHK("apply_A");
     return ETC_OK;
   }

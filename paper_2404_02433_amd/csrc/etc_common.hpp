@@ -93,4 +93,23 @@ template <class C> __device__ __forceinline__ C harm(C k1, C k2) {
   return C(2) * k1 * k2 / (k1 + k2);
 }
 
+// Reciprocal: hardware estimate refined by two Newton steps (within one ulp
+// of the correctly rounded quotient for positive normal arguments).
+__device__ __forceinline__ double frcp(double u) {
+  double r = __builtin_amdgcn_rcp(u);
+  double e = fma(-u, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-u, r, 1.0);
+  return fma(r, e, r);
+}
+// float32: the hardware reciprocal (1 ulp)
+__device__ __forceinline__ float frcp(float u) { return __builtin_amdgcn_rcpf(u); }
+
+// Face coefficient of the hot operator: the harmonic mean through the
+// reciprocal above.  Symmetric in its arguments bit for bit (the product and
+// the sum commute, the factor 2 is exact).
+template <class C> __device__ __forceinline__ C hface(C k1, C k2) {
+  return C(2) * k1 * k2 * frcp(k1 + k2);
+}
+
 }  // namespace etc

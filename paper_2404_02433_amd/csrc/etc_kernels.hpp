@@ -381,6 +381,170 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
   }
 }
 
+// Isotropic operator with every face coefficient computed once: block (64, 4)
+// owns the same 64 (b) x 16 (a) tiles as k_apply_A, but thread (x, y) holds the
+// four consecutive rows a0 + 4y .. a0 + 4y + 3 of column b0 + x.  Load-axis
+// faces are carried from one plane to the next, the faces between a thread's
+// own rows are shared in registers (five a faces per four voxels), each b
+// face is computed by its left voxel and passed on by a lane shift, and the
+// four faces left of a wave's first column by lanes 0..3.  Out-of-range
+// neighbours read finite defaults from LDS and get a zero coefficient.
+template <class S>
+__global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const S* __restrict__ w, Kap<S> kp, S* __restrict__ q,
+                                                     double* __restrict__ partials, const DevState* __restrict__ st,
+                                                     int gate, int kchunk) {
+  using C = S;
+  const int ntile = gridDim.x * gridDim.y * gridDim.z;
+  const int tile = xcd_tile(flat_block(), ntile);
+  const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
+  const int nch = (g.nL + kchunk - 1) / kchunk;
+  const int inst = bz / nch, chunk = bz - inst * nch;
+  if (st) st += inst;
+  if (gated_out(st, gate)) return;
+  {
+    const int64_t off = (int64_t)inst * g.V;
+    w += off;
+    q += off;
+    kp.shift(off);
+  }
+  __shared__ C tw_[ATA + 2][ATB + 2];
+  __shared__ C tk_[ATA + 2][ATB + 2];
+  __shared__ double red[16];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int b0 = bx * ATB, a0 = by * ATA;
+  const int b = b0 + tx;
+  const int k0 = chunk * kchunk;
+  const int k1 = min(g.nL, k0 + kchunk);
+  const S* __restrict__ ks = kp.L;
+  const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
+  const int64_t plane = g.plane;
+  const bool bok = b < g.nb;
+  const int abase = a0 + ARPT * ty;  // first row of this thread
+  const int rbase = 1 + ARPT * ty;   // its LDS row
+  bool rok[ARPT];
+  int64_t col[ARPT];
+#pragma unroll
+  for (int j = 0; j < ARPT; ++j) {
+    rok[j] = bok && (abase + j) < g.na;
+    col[j] = (int64_t)(abase + j) * g.nb + b;
+  }
+  // halo slot of this thread (always written: loaded value or a default):
+  // top row (ty 0), bottom row (ty 1), left column (ty 2, tx < 16), right
+  // column (ty 3, tx < 16)
+  int hr = -1, hc = 0;
+  bool hok = false;
+  int64_t hcol = 0;
+  {
+    int ha = -1, hb = -1;
+    if (ty == 0) { ha = a0 - 1; hb = b; hr = 0; hc = tx + 1; }
+    else if (ty == 1) { ha = a0 + ATA; hb = b; hr = ATA + 1; hc = tx + 1; }
+    else if (tx < ATA) { ha = a0 + tx; hb = (ty == 2) ? b0 - 1 : b0 + ATB; hr = tx + 1; hc = (ty == 2) ? 0 : ATB + 1; }
+    hok = hr >= 0 && ha >= 0 && ha < g.na && hb >= 0 && hb < g.nb;
+    if (hok) hcol = (int64_t)ha * g.nb + hb;
+  }
+  auto ld = [&](const S* __restrict__ arr, int k, int64_t c, bool ok, C dflt) -> C {
+    return (ok && k >= 0 && k < g.nL) ? (C)arr[(int64_t)k * plane + c] : dflt;
+  };
+  // which faces exist
+  const bool bl_ok = b0 + tx > 0, br_ok = b + 1 < g.nb;
+  bool fa_ok[ARPT + 1];
+#pragma unroll
+  for (int i = 0; i <= ARPT; ++i) {
+    const int ar = abase + i;  // face between rows ar - 1 and ar
+    fa_ok[i] = ar >= 1 && ar < g.na;
+  }
+  C wm[ARPT], wc[ARPT], kc[ARPT], wn[ARPT], kn[ARPT], tdn[ARPT];
+#pragma unroll
+  for (int j = 0; j < ARPT; ++j) {
+    wm[j] = ld(w, k0 - 1, col[j], rok[j], C(0));
+    const C km = ld(ks, k0 - 1, col[j], rok[j], C(1));
+    wc[j] = ld(w, k0, col[j], rok[j], C(0));
+    kc[j] = ld(ks, k0, col[j], rok[j], C(1));
+    wn[j] = ld(w, k0 + 1, col[j], rok[j], C(0));
+    kn[j] = ld(ks, k0 + 1, col[j], rok[j], C(1));
+    // face below plane k0: interior harmonic mean or the Dirichlet face 2 kappa
+    tdn[j] = (k0 > 0) ? hface(km, kc[j]) : C(2) * kc[j];
+  }
+  C hw = ld(w, k0, hcol, hok, C(0)), hk = ld(ks, k0, hcol, hok, C(1));
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    // prefetch: centres of plane k+2, halo of plane k+1
+    C wnn[ARPT], knn[ARPT];
+    const bool more = k + 1 < k1;
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      wnn[j] = ld(w, k + 2, col[j], rok[j] && more, C(0));
+      knn[j] = ld(ks, k + 2, col[j], rok[j] && more, C(1));
+    }
+    const C hwn = ld(w, k + 1, hcol, hok && more, C(0)), hkn = ld(ks, k + 1, hcol, hok && more, C(1));
+    __syncthreads();  // previous plane's LDS reads are done
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      tw_[rbase + j][1 + tx] = wc[j];
+      tk_[rbase + j][1 + tx] = kc[j];
+    }
+    if (hr >= 0) {
+      tw_[hr][hc] = hw;
+      tk_[hr][hc] = hk;
+    }
+    __syncthreads();
+    const int cc = 1 + tx;
+    // load-axis face above this plane (Dirichlet face 2 kappa on the last layer)
+    C tup[ARPT];
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) tup[j] = (k + 1 < g.nL) ? hface(kc[j], kn[j]) : C(2) * kc[j];
+    // a faces: fa_[i] between rows i - 1 and i of this thread (i = 0: the row above)
+    C fav[ARPT + 1];
+    fav[0] = fa_ok[0] ? hface(tk_[rbase - 1][cc], kc[0]) : C(0);
+#pragma unroll
+    for (int i = 1; i < ARPT; ++i) fav[i] = fa_ok[i] ? hface(kc[i - 1], kc[i]) : C(0);
+    fav[ARPT] = fa_ok[ARPT] ? hface(kc[ARPT - 1], tk_[rbase + ARPT][cc]) : C(0);
+    // b faces: right face here, left face from the lane to the left; lanes
+    // 0..3 compute the faces left of column b0 for rows 0..3 of this wave
+    C fr[ARPT], fl[ARPT];
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) fr[j] = br_ok ? hface(kc[j], tk_[rbase + j][cc + 1]) : C(0);
+    const int hl = tx & (ARPT - 1);
+    const C edge = hface(tk_[rbase + hl][0], tk_[rbase + hl][1]);
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      const C up = __shfl_up(fr[j], 1, 64);
+      const C e = __shfl(edge, j, 64);
+      fl[j] = bl_ok ? (tx == 0 ? e : up) : C(0);
+    }
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      const int r = rbase + j;
+      const C w0 = wc[j];
+      const C wa_ = (j == 0) ? tw_[r - 1][cc] : wc[j - 1];
+      const C wb_ = (j == ARPT - 1) ? tw_[r + 1][cc] : wc[j + 1];
+      C qv = fL * (tdn[j] * (w0 - wm[j]) + tup[j] * (w0 - wn[j]));
+      qv += fa * (fav[j] * (w0 - wa_) + fav[j + 1] * (w0 - wb_));
+      qv += fb * (fl[j] * (w0 - tw_[r][cc - 1]) + fr[j] * (w0 - tw_[r][cc + 1]));
+      if (rok[j]) {
+        const S qs = (S)qv;
+        q[(int64_t)k * plane + col[j]] = qs;
+        acc += (double)w0 * (double)qs;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < ARPT; ++j) {
+      tdn[j] = tup[j];
+      wm[j] = wc[j];
+      wc[j] = wn[j];
+      kc[j] = kn[j];
+      wn[j] = wnn[j];
+      kn[j] = knn[j];
+    }
+    hw = hwn;
+    hk = hkn;
+  }
+  if (partials) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[tile] = s;
+  }
+}
+
 // r = b - A p in double arithmetic (p double, kappa at its input precision),
 // stored at S precision, with the partial ||r||^2.  Columns of 64 b x 4 a
 // march along k; lateral neighbours come through the caches (tiles
@@ -833,15 +997,6 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
 }
 
 // =================================================================== Thomas
-// Reciprocal: hardware estimate refined by two Newton steps (within one ulp
-// of the correctly rounded quotient for the positive, normal pivots here).
-__device__ __forceinline__ double frcp(double u) {
-  double r = __builtin_amdgcn_rcp(u);
-  double e = fma(-u, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-u, r, 1.0);
-  return fma(r, e, r);
-}
 
 // Solve T_{a',b'} z = t along k for every transverse mode (a', b'), in place,
 // with double arithmetic.  T = s I + kL tridiag(-1, 2, -1), first and last
