@@ -34,27 +34,28 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per voxel and launch of each hot kernel (reads +
 # writes of the arrays it must touch), by storage precision.
-#   1 operator:           w, kappa -> q                         3 vectors
-#   2 update + DCT_b:     x, w, r, q -> x, r, t                 7 vectors (x = p in FP64,
+#   1 operator:             w, kappa -> q                       3 vectors
+#   2 residual + DCT_b:     r, q -> r, t                        4 vectors
+#   3 DCT_a forward:        t -> t                              2 vectors
+#   4 tridiagonal:          t -> t                              2 vectors
+#   5 DCT_a backward:       t -> t                              2 vectors
+#   6 DCT_b^-1, solution and direction:
+#                           t, w, x -> w, x                     5 vectors (x = p in FP64,
 #                                                              the float32 increment in mixed)
-#   3 DCT_a forward:      t -> t                                2 vectors
-#   4 tridiagonal:        t -> t                                2 vectors
-#   5 DCT_a backward:     t -> t                                2 vectors
-#   6 DCT_b^-1 + direction: t, w -> w                           3 vectors
-KERNEL_NAMES = {1: "k_apply_A", 2: "k_rows_fwd (update + DCT_b)", 3: "k_cols (DCT_a forward)",
-                4: "k_thomas", 5: "k_cols (DCT_a backward)", 6: "k_rows_inv (DCT_b^-1 + direction)"}
+KERNEL_NAMES = {1: "k_apply_A_iso", 2: "k_rows_fwd (residual update + DCT_b)", 3: "k_cols (DCT_a forward)",
+                4: "k_thomas", 5: "k_cols (DCT_a backward)", 6: "k_rows_inv (DCT_b^-1 + solution + direction)"}
 
 
 def bytes_per_voxel(kernel: int, es: int) -> int:
-    return {1: 3 * es, 2: 7 * es, 3: 2 * es, 4: 2 * es, 5: 2 * es, 6: 3 * es}[kernel]
+    return {1: 3 * es, 2: 4 * es, 3: 2 * es, 4: 2 * es, 5: 2 * es, 6: 5 * es}[kernel]
 
 
 def iteration_bytes_per_voxel(es: int, mixed: bool, refine_every: int) -> float:
     b = sum(bytes_per_voxel(k, es) for k in range(1, 7))
     if mixed and refine_every > 0:
-        # flush (p double r/w, increment r/w), true residual (p, kappa, r),
-        # redo of DCT_b (r -> t), every refine_every passes
-        b += (16 + 2 * es + 8 + 2 * es + 2 * es) / refine_every
+        # flush (p double r/w, increment r/w, w read), true residual (p,
+        # kappa, r), redo of DCT_b (r -> t), every refine_every passes
+        b += (16 + 3 * es + 8 + 2 * es + 2 * es) / refine_every
     return b
 
 

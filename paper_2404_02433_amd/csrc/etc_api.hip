@@ -480,24 +480,24 @@ template <class S> struct Ops {
   // DCT launches: compile-time kernels for the common lengths, else the
   // run-time-shaped ones.
   template <int MODE>
-  static void rows_fwd(etc_plan* P, const S* src, S* dst, S* x, const S* w, S* r, const S* q, double* partials,
-                       const DevState* st, int gate) {
+  static void rows_fwd(etc_plan* P, const S* src, S* dst, S* r, const S* q, double* partials, const DevState* st,
+                       int gate) {
     const LaunchCfg& lc = P->lc;
     const cx<T>* twb = (const cx<T>*)P->tw_b;
     with_ct_len<T, true>(P->dpb.N, lc.rpb, [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       k_rows_fwd<S, T, MODE, NC><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(
-          P->g, P->dpb, twb, src, dst, lc.rpb, lc.nrows, x, w, r, q, partials, st, gate);
+          P->g, P->dpb, twb, src, dst, lc.rpb, lc.nrows, r, q, partials, st, gate);
     });
   }
   template <int MODE>
-  static void rows_inv(etc_plan* P, const S* src, S* dst, const DevState* st, int gate) {
+  static void rows_inv(etc_plan* P, const S* src, S* dst, S* x, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     const cx<T>* twb = (const cx<T>*)P->tw_b;
     with_ct_len<T, true>(P->dpb.N, lc.rpb, [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       k_rows_inv<S, T, MODE, NC><<<lc.gridRows, kThreads, lc.ldsRows, P->stream>>>(P->g, P->dpb, twb, src, dst,
-                                                                                 lc.rpb, lc.nrows, st, gate);
+                                                                                 lc.rpb, lc.nrows, x, st, gate);
     });
   }
   template <int DIR>
@@ -591,11 +591,11 @@ template <class S> struct Ops {
 
   // Preconditioner of the initial pass (and of etc_apply_Minv):
   // t = DCT_b(src); t = DCT_a(t); Thomas; t = DCT_a^{-1}(t); dst = DCT_b^{-1}(t).
-  static etc_status precond(etc_plan* P, const S* src, S* dst, int inv_mode, const DevState* st, int gate,
+  static etc_status precond(etc_plan* P, const S* src, S* dst, const DevState* st, int gate,
                             int fin_op) {
     const LaunchCfg& lc = P->lc;
     S* t = (S*)P->t;
-    rows_fwd<0>(P, src, t, nullptr, nullptr, nullptr, nullptr, nullptr, st, gate);
+    rows_fwd<0>(P, src, t, nullptr, nullptr, nullptr, st, gate);
     LAUNCHCHK("rows_fwd");
     cols<-1>(P, t, st, gate);
     LAUNCHCHK("cols_fwd");
@@ -605,8 +605,7 @@ template <class S> struct Ops {
     if (s) return s;
     cols<+1>(P, t, st, gate);
     LAUNCHCHK("cols_inv");
-    if (inv_mode == 1) rows_inv<1>(P, t, dst, st, gate);
-    else rows_inv<0>(P, t, dst, st, gate);
+    rows_inv<0>(P, t, dst, nullptr, st, gate);
     LAUNCHCHK("rows_inv");
     return ETC_OK;
   }
@@ -640,16 +639,25 @@ template <class S> struct Ops {
       LAUNCHCHK("dir");
       return ETC_OK;
     }
-    return precond(P, r, w, 0, P->st, 1, FIN_RHO0);
+    return precond(P, r, w, P->st, 1, FIN_RHO0);
   }
 
   // The vector the update step accumulates into: p (FP64) or the float32
   // increment (mixed).
   static S* xsol(etc_plan* P) { return P->dlt ? (S*)P->dlt : (S*)(void*)P->p; }
 
-  static etc_status flush(etc_plan* P) {
-    k_flush<<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, (float*)P->dlt, P->st);
+  // fold the float32 increment (and, with_w, this pass's alpha w) into p
+  static etc_status flush(etc_plan* P, bool with_w) {
+    k_flush<<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, (float*)P->dlt,
+                                                           with_w ? (const float*)P->w : nullptr, P->st);
     LAUNCHCHK("flush");
+    return ETC_OK;
+  }
+
+  // the solution update a pass that stopped at its residual test left undone
+  static etc_status fixup(etc_plan* P) {
+    k_fixup<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, xsol(P), (const S*)P->w, P->st);
+    LAUNCHCHK("fixup");
     return ETC_OK;
   }
 
@@ -667,7 +675,7 @@ template <class S> struct Ops {
     LAUNCHCHK("update");
     if ((s = fin(P, FIN_RR, lc.nStride, lc.nStride))) return s;
     if (P->prec == ETC_MIXED) {
-      if ((s = flush(P))) return s;
+      if ((s = flush(P, false))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
       if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
     }
@@ -694,19 +702,19 @@ template <class S> struct Ops {
     timer_end(P, 1);
     if (s) return s;
     if ((s = fin(P, FIN_ALPHA, lc.nA, lc.nA))) return s;
-    // x += alpha w, r -= alpha q, ||r||^2, t = DCT_b(r)
+    // r -= alpha q, ||r||^2, t = DCT_b(r)
     timer_begin(P, 2);
-    rows_fwd<1>(P, nullptr, t, xsol(P), w, r, q, P->partials, P->st, 1);
+    rows_fwd<1>(P, nullptr, t, r, q, P->partials, P->st, 1);
     timer_end(P, 2);
     LAUNCHCHK("update_rows_fwd");
     if ((s = fin(P, FIN_RR, lc.nRows, lc.nRows))) return s;
     if (P->prec == ETC_MIXED) {
-      // fold the increment into p, replace r by the float64 true residual
-      // when requested, and redo DCT_b
-      if ((s = flush(P))) return s;
+      // fold the increment and alpha w into p, replace r by the float64 true
+      // residual when requested, and redo DCT_b
+      if ((s = flush(P, true))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
       if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
-      rows_fwd<0>(P, r, t, nullptr, nullptr, nullptr, nullptr, nullptr, P->st, 2);
+      rows_fwd<0>(P, r, t, nullptr, nullptr, nullptr, P->st, 2);
       LAUNCHCHK("rows_fwd_refine");
     }
     timer_begin(P, 3);
@@ -724,7 +732,7 @@ template <class S> struct Ops {
     LAUNCHCHK("cols_inv");
     // w = DCT_b^{-1}(t) + beta w
     timer_begin(P, 6);
-    rows_inv<1>(P, t, w, P->st, 1);
+    rows_inv<1>(P, t, w, xsol(P), P->st, 1);
     timer_end(P, 6);
     LAUNCHCHK("rows_inv_dir");
     return ETC_OK;
@@ -1196,6 +1204,11 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
     }
     enq += chunk;
   }
+  if (P->opt.precond == ETC_PC_DCT) {
+    s = (P->prec == ETC_MIXED) ? Ops<float>::fixup(P) : Ops<double>::fixup(P);
+    if (s) return s;
+    HIPCHK(hipStreamSynchronize(P->stream));
+  }
   int iters = 0, status = ST_OK;
   for (int i = 0; i < P->nseg; ++i) {
     const DevState& h = P->st_host[i];
@@ -1365,8 +1378,8 @@ etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
     if (rz) return fail(ETC_E_UNSUPPORTED, "no dot without a preconditioner");
     return ETC_OK;
   }
-  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::precond(P, (const float*)r, (float*)z, 0, P->st, 0, FIN_ACC3)
-                                        : Ops<double>::precond(P, (const double*)r, (double*)z, 0, P->st, 0, FIN_ACC3);
+  etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::precond(P, (const float*)r, (float*)z, P->st, 0, FIN_ACC3)
+                                        : Ops<double>::precond(P, (const double*)r, (double*)z, P->st, 0, FIN_ACC3);
   if (s) return s;
   if (rz) {
     if ((s = pull_state(P))) return s;

@@ -43,7 +43,7 @@ struct DevState {
   int max_iter;
   int refine_every;    // 0: never (FP64 form)
   int mixed;
-  int pad;
+  int pending;         // 1: the last pass's x += alpha w is still to be applied
 };
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = -4 };

@@ -647,16 +647,15 @@ __host__ __device__ constexpr int batch_of(int whole, int cap, int dflt) {
 }
 
 // Rows are the contiguous b lines; a block owns `rpb` whole rows.
-// MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): x += alpha w,
-// r -= alpha q, partial ||r||^2, t = DCT_b(r).  x is the solution p in the
-// FP64 form and the float32 increment since the last refinement in the
-// mixed form (flushed into the float64 p by k_flush).
+// MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): r -= alpha q, partial
+// ||r||^2, t = DCT_b(r).  (The solution update x += alpha w is done by the
+// backward row transform, which reads w anyway.)
 template <class S, class T, int MODE, int NC = 0>
 __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
-                                                  S* __restrict__ p, const S* __restrict__ w, S* __restrict__ r,
-                                                  const S* __restrict__ q, double* __restrict__ partials,
-                                                  const DevState* __restrict__ st, int gate) {
+                                                  S* __restrict__ r, const S* __restrict__ q,
+                                                  double* __restrict__ partials, const DevState* __restrict__ st,
+                                                  int gate) {
   using Sh = DctShape<T, NC>;
   // instance blockIdx.y of a batch
   if (st) st += blockIdx.y;
@@ -666,8 +665,6 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
     if (src) src += off;
     dst += off;
     if (MODE == 1) {
-      p += off;
-      w += off;
       r += off;
       q += off;
       partials += (int64_t)blockIdx.y * gridDim.x;
@@ -692,18 +689,21 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
   if (MODE == 1) alpha = st->alpha;
   // load (and update) the rows into LDS, reordered for the FFT route; each
   // batch issues all its loads before the first use (64 registers of values)
-  constexpr int U = (MODE == 1) ? batch_of(Sh::row_elems, 64 / (2 * (int)sizeof(S)), 4)
+  constexpr int U = (MODE == 1) ? batch_of(Sh::row_elems, 32 / ((int)sizeof(S) / 4), 4)
                                 : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
+  auto put = [&](int e, T v) {
+    const int line = e / N, j = e - line * N;
+    T* L = reinterpret_cast<T*>(buf + line * ls);
+    if (fft) L[vpos(dct_perm(j, N))] = v;
+    else L[j] = v;
+  };
   for (int e0 = tid; e0 < total; e0 += nthr * U) {
-    T x[U];
     if (MODE == 1) {
-      S pv[U], wv[U], rv[U], qv[U];
+      S rv[U], qv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
-          pv[u] = p[base + e];
-          wv[u] = w[base + e];
           rv[u] = r[base + e];
           qv[u] = q[base + e];
         }
@@ -712,28 +712,23 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
         if (e < total) {
-          p[base + e] = (S)((double)pv[u] + alpha * (double)wv[u]);
           const S rs = (S)((double)rv[u] - alpha * (double)qv[u]);
           r[base + e] = rs;
           acc += (double)rs * (double)rs;
-          x[u] = (T)rs;
+          put(e, (T)rs);
         }
       }
     } else {
+      S xv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * nthr;
-        if (e < total) x[u] = (T)src[base + e];
+        if (e < total) xv[u] = src[base + e];
       }
-    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * nthr;
-      if (e < total) {
-        const int line = e / N, j = e - line * N;
-        T* L = reinterpret_cast<T*>(buf + line * ls);
-        if (fft) L[vpos(dct_perm(j, N))] = x[u];
-        else L[j] = x[u];
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < total) put(e, (T)xv[u]);
       }
     }
   }
@@ -764,11 +759,14 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
 }
 
 // Inverse along rows.  MODE 0: dst = DCT_b^{-1}(src).  MODE 1: dst holds w on
-// entry and leaves with w = z + beta w, z = DCT_b^{-1}(src) (never stored).
+// entry; x += alpha w (the solution update of this pass; skipped when a
+// refinement already folded it into p), then w = z + beta w with
+// z = DCT_b^{-1}(src) (never stored).  x is the solution p in the FP64 form
+// and the float32 increment since the last refinement in the mixed form.
 template <class S, class T, int MODE, int NC = 0>
 __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
-                                                  const DevState* __restrict__ st, int gate) {
+                                                  S* __restrict__ xs, const DevState* __restrict__ st, int gate) {
   using Sh = DctShape<T, NC>;
   if (st) st += blockIdx.y;
   if (gated_out(st, gate)) return;
@@ -776,6 +774,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
     const int64_t off = (int64_t)blockIdx.y * g.V;
     src += off;
     dst += off;
+    if (MODE == 1) xs += off;
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -790,8 +789,11 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
   const int lines = (int)min((int64_t)rpbv, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
   const int total = lines * N;
-  double beta = 0.0;
-  if (MODE == 1) beta = st->beta;
+  double beta = 0.0, alpha = 0.0;
+  if (MODE == 1) {
+    beta = st->beta;
+    alpha = st->refine ? 0.0 : st->alpha;  // a refinement already moved p
+  }
   if (fft) {
     const int nit = M / 2 + 1;
     const int items = lines * nit;
@@ -825,14 +827,18 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
     if constexpr (Sh::ct) lds_fft_ct<T, +1, Sh::M, Sh::rows, nthr, Sh::ls>(buf, tw, tid);
     else lds_fft<T, +1>(buf, lines, ls, dp, tw, tid, nthr);
     const T invM = T(1) / T(M);
-    constexpr int UO = batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
+    constexpr int UO = (MODE == 1) ? batch_of(Sh::row_elems, 32 / ((int)sizeof(S) / 4), UNR / 2)
+                                   : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
     for (int e0 = tid; e0 < total; e0 += nthr * UO) {
-      S wv[UO];
+      S wv[UO], xv[UO];
       if (MODE == 1) {
 #pragma unroll
         for (int u = 0; u < UO; ++u) {
           const int e = e0 + u * nthr;
-          if (e < total) wv[u] = dst[base + e];
+          if (e < total) {
+            wv[u] = dst[base + e];
+            xv[u] = xs[base + e];
+          }
         }
       }
 #pragma unroll
@@ -842,8 +848,12 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
           const int line = e / N, j = e - line * N;
           const T* L = reinterpret_cast<const T*>(buf + line * ls);
           const T z = L[vpos(dct_perm(j, N))] * invM;
-          if (MODE == 1) dst[base + e] = (S)((double)z + beta * (double)wv[u]);
-          else dst[base + e] = (S)z;
+          if (MODE == 1) {
+            xs[base + e] = (S)((double)xv[u] + alpha * (double)wv[u]);
+            dst[base + e] = (S)((double)z + beta * (double)wv[u]);
+          } else {
+            dst[base + e] = (S)z;
+          }
         }
       }
     }
@@ -863,8 +873,13 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
       for (int k = 1; k < N; ++k) s += L[k] * tw[((2 * n + 1) * k) % N4].re;
       const T z = sc * s;
       const int64_t gi = base + e;
-      if (MODE == 1) dst[gi] = (S)((double)z + beta * (double)dst[gi]);
-      else dst[gi] = (S)z;
+      if (MODE == 1) {
+        const double wv = (double)dst[gi];
+        xs[gi] = (S)((double)xs[gi] + alpha * wv);
+        dst[gi] = (S)((double)z + beta * wv);
+      } else {
+        dst[gi] = (S)z;
+      }
     }
   }
 }
@@ -1313,12 +1328,16 @@ __global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__
       }
       const bool conv = rel <= st->rtol;
       if (!st->mixed) {
+        // the solution update of this pass happens in the backward row
+        // transform, which no longer runs: leave it to the fix-up kernel
         if (conv) {
           st->done = 1;
           st->status = ST_OK;
+          st->pending = 1;
         } else if (it >= st->max_iter) {
           st->done = 1;
           st->status = ST_NOT_CONVERGED;
+          st->pending = 1;
         }
       } else {
         st->refine = (conv || it >= st->max_iter || (st->refine_every > 0 && it % st->refine_every == 0)) ? 1 : 0;
@@ -1526,16 +1545,37 @@ __global__ __launch_bounds__(256) void k_dir_plain(Geo g, const S* __restrict__ 
 
 // Mixed form, at a refinement: p += increment, increment = 0 (float64 p).
 __global__ __launch_bounds__(256) void k_flush(Geo g, double* __restrict__ p, float* __restrict__ dlt,
-                                               const DevState* __restrict__ st) {
+                                               const float* __restrict__ w, const DevState* __restrict__ st) {
   st += blockIdx.y;
   if (st->done || !st->refine) return;
   p += (int64_t)blockIdx.y * g.V;
   dlt += (int64_t)blockIdx.y * g.V;
+  if (w) w += (int64_t)blockIdx.y * g.V;
+  // w given: this pass's alpha w is folded in here too (the backward row
+  // transform then skips it)
+  const double alpha = w ? st->alpha : 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    p[i] += (double)dlt[i];
+    double v = p[i] + (double)dlt[i];
+    if (w) v += alpha * (double)w[i];
+    p[i] = v;
     dlt[i] = 0.0f;
   }
+}
+
+// x += alpha w for the instances whose last pass ended before its backward
+// row transform (the float64 form stops right after the residual test).
+template <class S>
+__global__ __launch_bounds__(256) void k_fixup(Geo g, S* __restrict__ x, const S* __restrict__ w,
+                                               const DevState* __restrict__ st) {
+  st += blockIdx.y;
+  if (!st->pending) return;
+  x += (int64_t)blockIdx.y * g.V;
+  w += (int64_t)blockIdx.y * g.V;
+  const double alpha = st->alpha;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride)
+    x[i] = (S)((double)x[i] + alpha * (double)w[i]);
 }
 
 // Plain copy (bandwidth calibration of the hardware byte counters).
