@@ -293,7 +293,7 @@ __host__ __device__ constexpr int cols_tile(int M, int ls, int elt, bool fft) {
 // One radix-R Stockham stage over LINES lines of M points (line stride LS),
 // all shapes compile-time.  Same data flow as fft_stage.
 template <class T, int R, int DIR, int M, int NS, int LINES, int NTHR, int LS>
-__device__ __attribute__((noinline)) void fft_stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
   constexpr int per_line = M / R;
   constexpr int items = LINES * per_line;
   constexpr int step = M / (NS * R);

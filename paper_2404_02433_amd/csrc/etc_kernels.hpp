@@ -689,8 +689,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
   if (MODE == 1) alpha = st->alpha;
   // load (and update) the rows into LDS, reordered for the FFT route; each
   // batch issues all its loads before the first use (64 registers of values)
-  constexpr int U = (MODE == 1) ? batch_of(Sh::row_elems, 32 / ((int)sizeof(S) / 4), 4)
-                                : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
+  constexpr int U = (MODE == 1) ? batch_of(Sh::row_elems, 16, 4) : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
   auto put = [&](int e, T v) {
     const int line = e / N, j = e - line * N;
     T* L = reinterpret_cast<T*>(buf + line * ls);
@@ -829,8 +828,8 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
     const T invM = T(1) / T(M);
     constexpr int UO = (MODE == 1) ? batch_of(Sh::row_elems, 32 / ((int)sizeof(S) / 4), UNR / 2)
                                    : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
+    S wv[UO], xv[UO];
     for (int e0 = tid; e0 < total; e0 += nthr * UO) {
-      S wv[UO], xv[UO];
       if (MODE == 1) {
 #pragma unroll
         for (int u = 0; u < UO; ++u) {
@@ -886,15 +885,19 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
 
 // ========================================================= DCT along columns
 // Strided axis a, in place.  A block owns `tb` adjacent b columns of one
-// plane k = blockIdx.y: every LDS line is one column (length na).  Element e
+// plane: every LDS line is one column (length na).  Element e
 // of a block is (row n, column c) = (e / tb, e % tb); columns beyond the
 // right edge of the plane are skipped.
 template <class S, class T, int DIR, int NC = 0>
 __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
                                               int tb, const DevState* __restrict__ st, int gate) {
   using Sh = DctShape<T, NC>;
-  // blockIdx.y = global plane; instances of a batch hold nL planes each
-  if (st) st += blockIdx.y / g.nL;
+  // tile (column block bx, global plane) with tiles renumbered per XCD so
+  // that tiles sharing 128-byte lines run on one XCD together; instances of a
+  // batch hold nL planes each
+  const int tile = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bx = tile % gridDim.x, plane = tile / gridDim.x;
+  if (st) st += plane / g.nL;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -905,9 +908,9 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   const bool fft = Sh::ct ? true : (dp.fft != 0);
   const int ls = Sh::ct ? Sh::ls : dp.lstride;
   const int tbv = Sh::ct ? Sh::cols : tb;
-  const int b0 = blockIdx.x * tbv;
+  const int b0 = bx * tbv;
   const int lines = min(tbv, g.nb - b0);
-  S* pl = data + (int64_t)blockIdx.y * g.plane + b0;
+  S* pl = data + (int64_t)plane * g.plane + b0;
   const int total = tbv * N;
   if (DIR < 0) {
     constexpr int UC = batch_of(Sh::col_elems, 64 / ((int)sizeof(S) / 4), UNR);
