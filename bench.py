@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="grid edge (default: the 512^3 workload)")
     ap.add_argument("--rtol", type=float, default=1e-6)
-    ap.add_argument("--kernel", type=int, default=2, help="hot kernel timed with HIP events (1-6)")
+    ap.add_argument("--kernel", type=int, default=6, help="hot kernel timed with HIP events (1-6)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
