@@ -32,10 +32,10 @@ import numpy as np
 
 __all__ = [
     "canonical", "decanonical", "Problem", "make_problem",
-    "apply_A", "rhs", "dense_A",
+    "apply_A", "apply_A_at", "rhs", "dense_A",
     "family_extrema", "kref_mid", "lemma_bounds",
     "dct2", "dct3", "cos_matrix", "neumann_eigenvalues",
-    "thomas", "apply_Aref_inv", "dense_Aref",
+    "thomas", "apply_Aref_inv", "apply_Aref_at", "dense_Aref",
     "PCGResult", "pcg", "keff", "solve",
     "keff_gradient",
 ]
@@ -152,6 +152,35 @@ def apply_A(pb: Problem, p: np.ndarray) -> np.ndarray:
     q[0] += Tin * p[0]
     q[-1] += Tout * p[-1]
     return q
+
+
+def apply_A_at(pb: Problem, p: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """(A p) at the canonical voxels ``idx`` (rows of (k, a, b)), one voxel at
+    a time from the same definition as apply_A: for each of the six faces,
+    the harmonic mean of kappa~ of the two cells times (p_c - p_n) when the
+    neighbour exists, and 2 kappa~ p_c for a face on a Dirichlet layer.  For
+    sampled checks on grids too large for whole-array evaluation."""
+    hL, ha, hb = pb.h
+    sc = (hL ** -2, ha ** -2, hb ** -2)
+    comps = (pb.kap, pb.kapA, pb.kapB)
+    shape = pb.shape
+    out = np.empty(len(idx))
+    for n, (k, a, b) in enumerate(np.asarray(idx, dtype=np.int64)):
+        c = (k, a, b)
+        pc = p[c]
+        acc = 0.0
+        for d in range(3):
+            kc = comps[d][c] * sc[d]
+            for step in (-1, 1):
+                nb_ = list(c)
+                nb_[d] += step
+                if 0 <= nb_[d] < shape[d]:
+                    kn = comps[d][tuple(nb_)] * sc[d]
+                    acc += _harmonic(kc, kn) * (pc - p[tuple(nb_)])
+                elif d == 0:
+                    acc += 2.0 * kc * pc
+        out[n] = acc
+    return out
 
 
 def rhs(pb: Problem) -> np.ndarray:
@@ -323,6 +352,32 @@ def apply_Aref_inv(r: np.ndarray, kref: dict) -> np.ndarray:
     lo, dg, up = _T_diagonals(r.shape, kref)
     zh = thomas(lo, dg, up, rh)
     return dct3(dct3(zh, 2), 1)
+
+
+def apply_Aref_at(z: np.ndarray, kref: dict, idx: np.ndarray) -> np.ndarray:
+    """(A_ref z) at the canonical voxels ``idx``, one voxel at a time from
+    eq:refer bilinear forms: constant coefficients kappa_ref^L, ^a, ^b on the
+    internal faces normal to each axis, 2 kappa_ref^in and 2 kappa_ref^out on
+    the two Dirichlet layers, nothing on the Neumann faces."""
+    coef = (kref["L"], kref["a"], kref["b"])
+    shape = z.shape
+    out = np.empty(len(idx))
+    for n, (k, a, b) in enumerate(np.asarray(idx, dtype=np.int64)):
+        c = (k, a, b)
+        zc = z[c]
+        acc = 0.0
+        for d in range(3):
+            for step in (-1, 1):
+                nb_ = list(c)
+                nb_[d] += step
+                if 0 <= nb_[d] < shape[d]:
+                    acc += coef[d] * (zc - z[tuple(nb_)])
+        if k == 0:
+            acc += 2.0 * kref["in"] * zc
+        if k == shape[0] - 1:
+            acc += 2.0 * kref["out"] * zc
+        out[n] = acc
+    return out
 
 
 def dense_Aref(shape, kref: dict) -> np.ndarray:

@@ -1090,8 +1090,10 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
   };
 
   // PF: the next tile's rows are prefetched into registers (when they fit)
+  // tiles of one round are renumbered so that each XCD holds a contiguous
+  // range (adjacent tiles share 128-byte lines when TB * sizeof(S) < 128)
   S cur[MAXM], cur_s = S(0);
-  int tile = blockIdx.x;
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (PF && tile < ntiles) load(tile, cur, cur_s);
   for (; tile < ntiles; tile += gridDim.x) {
     S nxt[PF ? MAXM : 1], nxt_s = S(0);
