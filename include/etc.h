@@ -227,15 +227,18 @@ etc_status etc_apply_Minv(etc_plan* plan, const void* r, void* z, double* rz);
 
 /* Per-kernel timing with HIP events recorded around every launch of one hot
  * kernel on the plan's stream during etc_solve.  kernel_id: 0 off,
- * 1 operator, 2 update + forward row DCT, 3 forward column DCT,
- * 4 tridiagonal solve, 5 backward column DCT, 6 backward row DCT + direction.
+ * 1 operator, 2 residual update + forward row DCT, 3 forward column DCT,
+ * 4 tridiagonal solve, 5 backward column DCT, 6 backward row DCT + solution
+ * and direction updates.
  * etc_kernel_time returns the summed milliseconds and launch count of the
  * last solve. */
 etc_status etc_set_kernel_timer(etc_plan* plan, int kernel_id);
 etc_status etc_kernel_time(const etc_plan* plan, double* total_ms, int* launches);
 
-/* Device-to-device copy of n doubles by a plain streaming kernel (used to
- * calibrate hardware byte counters). */
+/* Device-to-device copy of n doubles by a plain streaming kernel (16-byte
+ * accesses): calibrates hardware byte counters and measures the streaming
+ * ceiling.  src and dst must be 16-byte aligned (else ETC_E_INVALID); the
+ * copy is enqueued on `stream` (hipStream_t, NULL = null stream). */
 etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream);
 
 void etc_destroy(etc_plan* plan);

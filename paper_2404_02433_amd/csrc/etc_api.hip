@@ -1406,7 +1406,9 @@ etc_status etc_kernel_time(const etc_plan* P, double* total_ms, int* launches) {
 
 etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream) {
   if (!src || !dst || n < 0) return fail(ETC_E_INVALID, "bad copy arguments");
-  int64_t gs = std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+    return fail(ETC_E_INVALID, "copy buffers must be 16-byte aligned");
+  int64_t gs = std::min<int64_t>((n / 2 + 4 * kThreads - 1) / (4 * kThreads), 16384);
   if (gs < 1) gs = 1;
   k_copy<<<(int)gs, kThreads, 0, (hipStream_t)stream>>>(src, dst, n);
   LAUNCHCHK("copy");

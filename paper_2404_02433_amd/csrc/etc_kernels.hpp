@@ -646,6 +646,15 @@ __host__ __device__ constexpr int batch_of(int whole, int cap, int dflt) {
   return whole > 0 ? (whole < cap ? whole : cap) : dflt;
 }
 
+// 16-byte vector of storage values (global loads and stores of 4 float32 or
+// 2 float64 per lane).
+template <class S> struct alignas(16) V16 {
+  static constexpr int n = 16 / (int)sizeof(S);
+  S v[n];
+};
+template <class S> __device__ __forceinline__ V16<S> ld16(const S* p) { return *reinterpret_cast<const V16<S>*>(p); }
+template <class S> __device__ __forceinline__ void st16(S* p, const V16<S>& x) { *reinterpret_cast<V16<S>*>(p) = x; }
+
 // Rows are the contiguous b lines; a block owns `rpb` whole rows.
 // MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): r -= alpha q, partial
 // ||r||^2, t = DCT_b(r).  (The solution update x += alpha w is done by the
@@ -696,6 +705,47 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
     if (fft) L[vpos(dct_perm(j, N))] = v;
     else L[j] = v;
   };
+  if constexpr (Sh::ct) {
+    // compile-time lengths (multiples of 4): 16-byte accesses, batches of
+    // UV vectors per thread
+    using Vt = V16<S>;
+    constexpr int VW = Vt::n;
+    constexpr int UV = (MODE == 1) ? 16 / VW : 32 / VW;
+    for (int v0 = tid; v0 * VW < total; v0 += nthr * UV) {
+      Vt a[UV], b[UV];
+#pragma unroll
+      for (int u = 0; u < UV; ++u) {
+        const int e = (v0 + u * nthr) * VW;
+        if (e < total) {
+          if (MODE == 1) {
+            a[u] = ld16(r + base + e);
+            b[u] = ld16(q + base + e);
+          } else {
+            a[u] = ld16(src + base + e);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UV; ++u) {
+        const int e = (v0 + u * nthr) * VW;
+        if (e < total) {
+          if (MODE == 1) {
+            Vt o;
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+              o.v[i] = (S)((double)a[u].v[i] - alpha * (double)b[u].v[i]);
+              acc += (double)o.v[i] * (double)o.v[i];
+              put(e + i, (T)o.v[i]);
+            }
+            st16(r + base + e, o);
+          } else {
+#pragma unroll
+            for (int i = 0; i < VW; ++i) put(e + i, (T)a[u].v[i]);
+          }
+        }
+      }
+    }
+  } else
   for (int e0 = tid; e0 < total; e0 += nthr * U) {
     if (MODE == 1) {
       S rv[U], qv[U];
@@ -828,6 +878,46 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
     const T invM = T(1) / T(M);
     constexpr int UO = (MODE == 1) ? batch_of(Sh::row_elems, 32 / ((int)sizeof(S) / 4), UNR / 2)
                                    : batch_of(Sh::row_elems, 64 / ((int)sizeof(S) / 4), UNR);
+    if constexpr (Sh::ct) {
+      // 16-byte accesses (compile-time lengths are multiples of 4)
+      using Vt = V16<S>;
+      constexpr int VW = Vt::n;
+      constexpr int UV = 32 / VW;
+      for (int v0 = tid; v0 * VW < total; v0 += nthr * UV) {
+        Vt wa[UV], xa[UV];
+        if (MODE == 1) {
+#pragma unroll
+          for (int u = 0; u < UV; ++u) {
+            const int e = (v0 + u * nthr) * VW;
+            if (e < total) {
+              wa[u] = ld16(dst + base + e);
+              xa[u] = ld16(xs + base + e);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+          const int e = (v0 + u * nthr) * VW;
+          if (e < total) {
+            const int line = e / N, j0 = e - line * N;
+            const T* L = reinterpret_cast<const T*>(buf + line * ls);
+            Vt wo, xo;
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+              const T z = L[vpos(dct_perm(j0 + i, N))] * invM;
+              if (MODE == 1) {
+                xo.v[i] = (S)((double)xa[u].v[i] + alpha * (double)wa[u].v[i]);
+                wo.v[i] = (S)((double)z + beta * (double)wa[u].v[i]);
+              } else {
+                wo.v[i] = (S)z;
+              }
+            }
+            st16(dst + base + e, wo);
+            if (MODE == 1) st16(xs + base + e, xo);
+          }
+        }
+      }
+    } else {
     S wv[UO], xv[UO];
     for (int e0 = tid; e0 < total; e0 += nthr * UO) {
       if (MODE == 1) {
@@ -855,6 +945,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
           }
         }
       }
+    }
     }
   } else {
     for (int e = tid; e < total; e += nthr) {
@@ -1584,9 +1675,23 @@ __global__ __launch_bounds__(256) void k_fixup(Geo g, S* __restrict__ x, const S
 }
 
 // Plain copy (bandwidth calibration of the hardware byte counters).
+// 16-byte accesses, four per thread in flight; src and dst 16-byte aligned.
 __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+  constexpr int U = 4;
+  const int64_t nv = n / 2;
+  const V16<double>* s2 = reinterpret_cast<const V16<double>*>(src);
+  V16<double>* d2 = reinterpret_cast<V16<double>*>(dst);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * U;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x; i0 < nv; i0 += stride) {
+    V16<double> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * blockDim.x < nv) v[u] = s2[i0 + u * blockDim.x];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * blockDim.x < nv) d2[i0 + u * blockDim.x] = v[u];
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) dst[n - 1] = src[n - 1];
 }
 
 }  // namespace etc
