@@ -145,7 +145,8 @@ def ensemble_bench(torch, etc, rvegen, args):
     kaps = [torch.as_tensor(k, device="cuda:0") for k in kaps_np]
     V = sum(k.size for k in kaps_np)
     form = args.forms.split(",")[0]
-    kw = dict(precision=form, rtol=args.rtol, use_graph=args.graph)
+    kw = dict(precision=form, rtol=args.rtol, use_graph=args.graph, concurrent=not args.serial,
+              max_batch_voxels=args.batch_voxels)
     for _ in range(args.warmup):
         etc.solve_ensemble(kaps, 0, **kw)
     torch.cuda.synchronize()
@@ -165,7 +166,8 @@ def ensemble_bench(torch, etc, rvegen, args):
         "data": "synthetic",
         "config": {"workload": f"grf_ensemble: {len(kaps)} log-normal GRF RVEs, edges 48/64/96/128/160, "
                                f"{V / 1e6:.1f} M voxels in total, load x, rtol {args.rtol:g}", "form": form,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "concurrent_plans": not args.serial,
+                   "max_batch_voxels": args.batch_voxels},
         "plans": out["plans"],
         "iters_min_max": [min(out["iters"]), max(out["iters"])],
         "all_ok": all(s == "ok" for s in out["status"]),
@@ -213,6 +215,8 @@ def main():
     ap.add_argument("--ensemble", type=int, default=0, metavar="COUNT",
                     help="time the mixed-size GRF ensemble of COUNT RVEs instead (RVEs/s)")
     ap.add_argument("--graph", action="store_true", help="replay the PCG passes from captured HIP graphs")
+    ap.add_argument("--serial", action="store_true", help="ensemble: run the batch plans one after another")
+    ap.add_argument("--batch-voxels", type=int, default=1 << 25, help="ensemble: voxel cap of one batch plan")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note"}))

@@ -357,13 +357,16 @@ def solve_batch(kappa, axis: int = 0, **kw) -> dict:
 
 
 def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_grad: bool = False,
-                   **kw) -> dict:
+                   concurrent: bool = True, **kw) -> dict:
     """K_eff of an ensemble of RVEs of mixed sizes.
 
     RVEs of one shape are stacked into batch plans (at most ``max_batch_voxels``
     voxels per plan), each solved with per-instance exit tests; results are
-    returned in input order.  With ``want_grad`` the gradients dK/dkappa are
-    returned too (one tensor per RVE)."""
+    returned in input order.  With ``concurrent`` the plans run at the same
+    time, each on a stream of its own driven by a host thread (small batches
+    then share the device instead of running one after another).  With
+    ``want_grad`` the gradients dK/dkappa are returned too (one tensor per
+    RVE)."""
     torch = _torch()
     buckets: dict = {}
     for i, k in enumerate(kappas):
@@ -375,24 +378,52 @@ def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_
            "relres": [None] * n, "plans": 0}
     if want_grad:
         out["grad"] = [None] * n
+    parts = []
     for (shape, _), idx in buckets.items():
         per = max(1, int(max_batch_voxels) // max(1, math.prod(shape)))
-        for c0 in range(0, len(idx), per):
-            part = idx[c0:c0 + per]
-            batch = torch.stack([kappas[i] for i in part])
-            plan = etc_setup_batch(batch, axis, want_grad=want_grad, **kw)
-            del batch
-            etc_solve(plan)
-            res = etc_batch_results(plan)
-            res.update(etc_keff_batch(plan))
-            g = etc_grad(plan) if want_grad else None
-            plan.close()
-            out["plans"] += 1
-            for j, i in enumerate(part):
-                for key in ("keff", "k_in", "iters", "status", "relres"):
-                    out[key][i] = res[key][j]
-                if want_grad:
-                    out["grad"][i] = g[j]
+        parts += [idx[c0:c0 + per] for c0 in range(0, len(idx), per)]
+    # largest batches first, so that the small ones fill in behind them
+    parts.sort(key=lambda part: -len(part) * kappas[part[0]].numel())
+    device = kappas[0].device if n else None
+
+    def run(part, stream):
+        batch = torch.stack([kappas[i] for i in part])
+        plan = etc_setup_batch(batch, axis, want_grad=want_grad, **kw)
+        del batch
+        etc_solve(plan)
+        res = etc_batch_results(plan)
+        res.update(etc_keff_batch(plan))
+        res["grad"] = etc_grad(plan) if want_grad else None
+        plan.close()
+        return res
+
+    def on_stream(part, stream):
+        with torch.cuda.stream(stream):
+            return run(part, stream)
+
+    if concurrent and len(parts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+
+        main = torch.cuda.current_stream(device)
+        streams = [torch.cuda.Stream(device) for _ in parts]  # default priority
+        for st in streams:
+            st.wait_stream(main)  # the inputs were written on the caller's stream
+        with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+            results = list(ex.map(on_stream, parts, streams))
+        for st in streams:
+            main.wait_stream(st)
+        if want_grad:
+            for res, st in zip(results, streams):
+                res["grad"].record_stream(main)
+    else:
+        results = [run(part, None) for part in parts]
+    for part, res in zip(parts, results):
+        out["plans"] += 1
+        for j, i in enumerate(part):
+            for key in ("keff", "k_in", "iters", "status", "relres"):
+                out[key][i] = res[key][j]
+            if want_grad:
+                out["grad"][i] = res["grad"][j]
     return out
 
 
