@@ -83,8 +83,8 @@ def measured_traffic(kernel: int, workload: str, precision: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def run_solve(etc, kap, precision, rtol, timer_kernel=0):
-    plan = etc.etc_setup(kap, 0, 1.0, 0.0, precision=precision, rtol=rtol)
+def run_solve(etc, kap, precision, rtol, timer_kernel=0, autotune=False):
+    plan = etc.etc_setup(kap, 0, 1.0, 0.0, precision=precision, rtol=rtol, autotune=autotune)
     if timer_kernel:
         etc.etc_set_kernel_timer(plan, timer_kernel)
     out = etc.etc_solve(plan)
@@ -95,14 +95,14 @@ def run_solve(etc, kap, precision, rtol, timer_kernel=0):
     return out
 
 
-def time_form(torch, etc, kap, precision, rtol, steps, warmup, timer_kernel):
+def time_form(torch, etc, kap, precision, rtol, steps, warmup, timer_kernel, autotune=False):
     for _ in range(warmup):
-        run_solve(etc, kap, precision, rtol)
+        run_solve(etc, kap, precision, rtol, autotune=autotune)
     torch.cuda.synchronize()
     outs = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        outs.append(run_solve(etc, kap, precision, rtol, timer_kernel))
+        outs.append(run_solve(etc, kap, precision, rtol, timer_kernel, autotune))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     return dt, outs
@@ -216,6 +216,8 @@ def main():
                     help="time the mixed-size GRF ensemble of COUNT RVEs instead (RVEs/s)")
     ap.add_argument("--graph", action="store_true", help="replay the PCG passes from captured HIP graphs")
     ap.add_argument("--serial", action="store_true", help="ensemble: run the batch plans one after another")
+    ap.add_argument("--autotune", action="store_true",
+                    help="plans tune their launch shapes at setup (the warm-up solve pays for the tuning)")
     ap.add_argument("--batch-voxels", type=int, default=1 << 25, help="ensemble: voxel cap of one batch plan")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -249,7 +251,7 @@ def main():
     res = {}
     for form in forms:
         print(f"bench: timing {form}", file=sys.stderr, flush=True)
-        dt, outs = time_form(torch, etc, kap, form, args.rtol, args.steps, args.warmup, args.kernel)
+        dt, outs = time_form(torch, etc, kap, form, args.rtol, args.steps, args.warmup, args.kernel, args.autotune)
         o = outs[-1]
         es = 4 if form == "mixed" else 8
         it_bytes = iteration_bytes_per_voxel(es, form == "mixed", 10) * V
@@ -287,7 +289,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"spheres512: {args.n}^3 two-phase RVE, r=10 non-overlapping spheres to "
                                f"vf>={0.26} ({info['spheres']} spheres, vf={info['vf']:.4f}), kappa 1/100, "
-                               f"load x, rtol {args.rtol:g}", "form": head},
+                               f"load x, rtol {args.rtol:g}", "form": head, "autotune": bool(args.autotune)},
         "forms": res,
         "keff_mixed_vs_fp64": (abs(res["mixed"]["keff"] - res["fp64"]["keff"]) / res["fp64"]["keff"]
                                if "mixed" in res and "fp64" in res else None),

@@ -91,6 +91,9 @@ typedef struct {
   size_t workspace_bytes;
   int want_grad;         /* 1: reserve the adjoint state for etc_grad (8 bytes per voxel) */
   etc_precond precond;   /* default ETC_PC_DCT */
+  int autotune;          /* 1: etc_setup times the stencil's plane chunk and the
+                            tridiagonal kernel's grid on the plan's own buffers and
+                            keeps the fastest (cached per problem shape); default 0 */
   int use_graph;         /* 1: etc_solve captures `poll_every` passes in a HIP graph on
                             first use (per solution buffer and Dirichlet pair) and
                             replays it; ignored while a kernel timer is set.  The
@@ -234,6 +237,10 @@ etc_status etc_apply_Minv(etc_plan* plan, const void* r, void* z, double* rz);
  * last solve. */
 etc_status etc_set_kernel_timer(etc_plan* plan, int kernel_id);
 etc_status etc_kernel_time(const etc_plan* plan, double* total_ms, int* launches);
+
+/* Launch shapes of a plan: the stencil's plane chunk, the tridiagonal
+ * kernel's blocks per instance, and whether the autotuner chose them. */
+etc_status etc_launch_info(const etc_plan* plan, int* kchunk, int* thomas_blocks, int* tuned);
 
 /* Device-to-device copy of n doubles by a plain streaming kernel (16-byte
  * accesses): calibrates hardware byte counters and measures the streaming

@@ -59,6 +59,7 @@ class _Options(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("want_grad", ctypes.c_int),
         ("precond", ctypes.c_int),
+        ("autotune", ctypes.c_int),
         ("use_graph", ctypes.c_int),
     ]
 
@@ -85,6 +86,8 @@ class _Result(ctypes.Structure):
 
 _SYMBOLS = {
     "etc_options_default": (None, [ctypes.POINTER(_Options)]),
+    "etc_launch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]),
     "etc_workspace_size": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]),
     "etc_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC, ctypes.c_int,
@@ -165,7 +168,8 @@ def _torch():
 
 
 def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_every=8, kref="mid",
-             kref_user=None, L=None, stream=None, want_grad=False, precond="dct", use_graph=False) -> _Options:
+             kref_user=None, L=None, stream=None, want_grad=False, precond="dct", use_graph=False,
+             autotune=False) -> _Options:
     lib = load_library()
     o = _Options()
     lib.etc_options_default(ctypes.byref(o))
@@ -185,6 +189,7 @@ def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_e
     o.want_grad = 1 if want_grad else 0
     o.precond = {"dct": 0, "none": 1}[precond]
     o.use_graph = 1 if use_graph else 0
+    o.autotune = 1 if autotune else 0
     return o
 
 
@@ -238,14 +243,16 @@ class Plan:
 def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
               rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
               kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, source=None,
-              p_in_face=None, p_out_face=None, precond: str = "dct", use_graph: bool = False) -> Plan:
+              p_in_face=None, p_out_face=None, precond: str = "dct", use_graph: bool = False,
+              autotune: bool = False) -> Plan:
     """Preparation phase on device data (user layout, load axis ``axis``).
 
     ``kappa`` is one tensor (isotropic) or a sequence of three tensors, the
     conductivity along user axes 0, 1, 2 (orthotropic), float64 or float32.
     ``source`` (float64, kappa's shape), ``p_in_face`` / ``p_out_face``
     (float64 over the two transverse axes in user order) are optional.
-    ``use_graph`` replays the PCG passes from a captured HIP graph."""
+    ``use_graph`` replays the PCG passes from a captured HIP graph;
+    ``autotune`` times launch-shape candidates at setup and keeps the fastest."""
     torch = _torch()
     comps = list(kappa) if isinstance(kappa, (list, tuple)) else [kappa]
     if len(comps) not in (1, 3):
@@ -262,7 +269,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
     dtype = "float64" if k0.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(k0.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad, precond, use_graph)
+                 want_grad, precond, use_graph, autotune)
     n = _dims(k0.shape)
     pr = _Problem()
     keep = list(comps)
@@ -299,7 +306,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
 def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
                     rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
                     kref: str = "mid", kref_user=None, L=None, want_grad: bool = False,
-                    precond: str = "dct", use_graph: bool = False) -> Plan:
+                    precond: str = "dct", use_graph: bool = False, autotune: bool = False) -> Plan:
     """Batch of same-size RVEs: ``kappa`` has shape (B, n0, n1, n2)."""
     torch = _torch()
     if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda" or kappa.dim() != 4:
@@ -310,7 +317,7 @@ def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0,
     dtype = "float64" if kappa.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(kappa.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad, precond, use_graph)
+                 want_grad, precond, use_graph, autotune)
     nb = int(kappa.shape[0])
     n = _dims(kappa.shape[1:])
     nbytes = ctypes.c_size_t(0)
@@ -544,6 +551,14 @@ def etc_kernel_time(plan: Plan):
     ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
     _check(load_library().etc_kernel_time(plan.handle, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def etc_launch_info(plan: Plan) -> dict:
+    """Launch shapes of a plan (stencil plane chunk, tridiagonal blocks per
+    instance) and whether the autotuner chose them."""
+    kc, tb, tu = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().etc_launch_info(plan.handle, ctypes.byref(kc), ctypes.byref(tb), ctypes.byref(tu)))
+    return {"kchunk": kc.value, "thomas_blocks": tb.value, "tuned": bool(tu.value)}
 
 
 def etc_copy_f64(src, dst):

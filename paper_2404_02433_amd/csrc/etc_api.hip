@@ -49,6 +49,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct LaunchCfg {
   // operator: block (64, 4) over 64 x 16 tiles; residual: 64 x 4 tiles
   dim3 gridA;
+  int nA_max;  // partials of the stencil at its smallest chunk (autotuner candidates)
   int kchunk, nA;
   dim3 gridR;
   int kchunkR, nR;
@@ -121,6 +122,7 @@ struct etc_plan {
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
+  int tuned;  // 1: launch shapes chosen by the autotuner
   // kernel timer
   int timer_id;
   std::vector<hipEvent_t> ev;
@@ -199,6 +201,15 @@ void canonical_dims(const int64_t n[3], int axis, int& nL, int& na, int& nb) {
   nb = o[1];
 }
 
+// Stencil launch for planes chunks of `kchunk` (tiles of 64 b x 16 a).
+void set_stencil_chunk(LaunchCfg& lc, const Geo& g, int kchunk) {
+  const int gx = (g.nb + 63) / 64, gy = (g.na + 15) / 16;
+  const int nch = (g.nL + kchunk - 1) / kchunk;
+  lc.kchunk = kchunk;
+  lc.gridA = dim3(gx, gy, nch * g.nseg);
+  lc.nA = gx * gy * nch;
+}
+
 LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt) {
   LaunchCfg lc{};
   const size_t cx_sz = 2 * elt;
@@ -213,6 +224,7 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   lc.kchunk = kchunk;
   lc.gridA = dim3(gx, gy, nch * ns);
   lc.nA = gx * gy * nch;
+  lc.nA_max = gx * gy * ((g.nL + std::min(8, g.nL) - 1) / std::min(8, g.nL));
   {
     const int gy4 = (g.na + 3) / 4;
     int kc4 = g.nL;
@@ -269,6 +281,7 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
 int max_partials_of(const LaunchCfg& lc) {
   int64_t m = 1024;
   m = std::max<int64_t>(m, lc.nA);
+  m = std::max<int64_t>(m, lc.nA_max);
   m = std::max<int64_t>(m, lc.nR);
   m = std::max<int64_t>(m, lc.nRows);
   m = std::max<int64_t>(m, lc.nThomas);
@@ -537,6 +550,84 @@ template <class S> struct Ops {
     else if (lc.maxm <= 16) f(&k_thomas<S, TB, PP, 16, false>);
     else if (lc.maxm <= 32) f(&k_thomas<S, TB, PP, 32, false>);
     else f(&k_thomas<S, TB, PP, 64, false>);
+  }
+
+  // Setup-time autotuner: time the stencil for plane chunks of 8 .. nL and
+  // the tridiagonal kernel for persistent grids of 1x and 2x the resident
+  // blocks and for one block per tile, on this plan's own buffers, and keep
+  // the fastest of each (cached per problem shape for the process).
+  struct Tuned {
+    int kchunk, thomas_x;
+  };
+  static etc_status autotune(etc_plan* P) {
+    static std::vector<std::pair<std::vector<int64_t>, Tuned>> cache;
+    LaunchCfg& lc = P->lc;
+    const Geo& g = P->g;
+    const std::vector<int64_t> key = {g.nL, g.na, g.nb, P->nseg, (int64_t)sizeof(S), P->ortho ? 1 : 0,
+                                      (int64_t)lc.gridThomas.x};
+    for (auto& e : cache)
+      if (e.first == key) {
+        set_stencil_chunk(lc, g, e.second.kchunk);
+        lc.gridThomas.x = e.second.thomas_x;
+        P->tuned = 1;
+        return ETC_OK;
+      }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    etc_status s = ETC_OK;
+    auto time_it = [&](auto&& launch) -> float {
+      launch();
+      (void)hipEventRecord(e0, P->stream);
+      for (int i = 0; i < 3; ++i) launch();
+      (void)hipEventRecord(e1, P->stream);
+      float ms = 0.0f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
+      return ms;
+    };
+    const size_t vb = (size_t)g.V * P->nseg * sizeof(S);
+    if (hipMemsetAsync(P->w, 0, vb, P->stream) != hipSuccess || hipMemsetAsync(P->t, 0, vb, P->stream) != hipSuccess)
+      s = fail(ETC_E_HIP, "autotune: memset failed");
+    // stencil chunk
+    Tuned best{lc.kchunk, (int)lc.gridThomas.x};
+    if (!s) {
+      float tbest = 1e30f;
+      for (int kc = std::min(8, g.nL);; kc *= 2) {
+        const int kcc = std::min(kc, g.nL);
+        set_stencil_chunk(lc, g, kcc);
+        if (lc.gridA.z <= 65535) {
+          const float ms = time_it([&] { (void)apply_A_launch(P, (const S*)P->w, (S*)P->q, nullptr, nullptr, 0); });
+          if (ms < tbest) {
+            tbest = ms;
+            best.kchunk = kcc;
+          }
+        }
+        if (kcc >= g.nL) break;
+      }
+      set_stencil_chunk(lc, g, best.kchunk);
+    }
+    // tridiagonal grid
+    if (!s) {
+      const int resident = (int)lc.gridThomas.x;
+      float tbest = 1e30f;
+      const int cands[3] = {resident, std::min(lc.nThomas, 2 * resident), lc.nThomas};
+      for (int c : cands) {
+        lc.gridThomas.x = c;
+        const float ms = time_it([&] { (void)thomas(P, (S*)P->t, nullptr, nullptr, 0); });
+        if (ms < tbest) {
+          tbest = ms;
+          best.thomas_x = c;
+        }
+      }
+      lc.gridThomas.x = best.thomas_x;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    HIPCHK(hipGetLastError());
+    cache.push_back({key, best});
+    P->tuned = 1;
+    return ETC_OK;
   }
 
   // Persistent grid of the tridiagonal kernel: the blocks that fit on the device at once.
@@ -809,6 +900,15 @@ void etc_options_default(etc_options* o) {
   o->want_grad = 0;
   o->precond = ETC_PC_DCT;
   o->use_graph = 0;
+  o->autotune = 0;
+}
+
+etc_status etc_launch_info(const etc_plan* P, int* kchunk, int* thomas_blocks, int* tuned) {
+  if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (kchunk) *kchunk = P->lc.kchunk;
+  if (thomas_blocks) *thomas_blocks = (int)P->lc.gridThomas.x;
+  if (tuned) *tuned = P->tuned;
+  return ETC_OK;
 }
 
 const char* etc_last_error(void) { return g_err.c_str(); }
@@ -980,6 +1080,11 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
   if (s) return bail(s);
   s = (P->prec == ETC_MIXED) ? Ops<float>::thomas_grid(P) : Ops<double>::thomas_grid(P);
   if (s) return bail(s);
+  P->tuned = 0;
+  if (o.autotune) {
+    s = (P->prec == ETC_MIXED) ? Ops<float>::autotune(P) : Ops<double>::autotune(P);
+    if (s) return bail(s);
+  }
   if (ps.faces) {
     // face data: [a][b] over the transverse axes in user order (constant pair where NULL)
     std::vector<double> pin((size_t)g.plane, bc.p_in), pout((size_t)g.plane, bc.p_out);

@@ -474,3 +474,27 @@ def test_ensemble_of_mixed_sizes_matches_oracle(concurrent):
         g = out["grad"][i].cpu().numpy()
         assert g.shape == k.shape
         assert np.abs(g - gref).max() <= 1e-7 * np.abs(gref).max(), i
+
+
+# ---------------------------------------------------------------- autotuner
+def test_autotuned_plan_reaches_the_same_solution():
+    """The setup-time autotuner only changes launch shapes: the solve reaches
+    the oracle's K_eff, and a second plan of the same shape reuses the
+    choice."""
+    kap = lognormal((40, 72, 48), seed=61, sigma=1.0)
+    ref = O.solve(kap, 0, rtol=1e-12)
+    for precision, tol in (("fp64", 1e-9), ("mixed", 1e-5)):
+        plan = etc.etc_setup(dev(kap), 0, rtol=1e-10 if precision == "fp64" else 1e-6, precision=precision,
+                             autotune=True)
+        info = etc.etc_launch_info(plan)
+        assert info["tuned"] and 1 <= info["kchunk"] <= 40 and info["thomas_blocks"] >= 1
+        etc.etc_solve(plan)
+        k = etc.etc_keff(plan)["keff"]
+        plan.close()
+        assert abs(k - ref["keff"]) <= tol * ref["keff"]
+        again = etc.etc_setup(dev(kap), 0, precision=precision, autotune=True)
+        assert etc.etc_launch_info(again) == info
+        again.close()
+    plain = etc.etc_setup(dev(kap), 0)
+    assert not etc.etc_launch_info(plain)["tuned"]
+    plain.close()
