@@ -720,7 +720,7 @@ template <class S> struct Ops {
       s = residual(P, r, nullptr, 0);
       if (s) return s;
       // relative residual of the warm start
-      if ((s = fin(P, FIN_RR0, lc.nR, lc.nR))) return s;
+      if ((s = fin(P, FIN_RR0, residual_parts(P), residual_parts(P)))) return s;
     }
     if (P->opt.precond == ETC_PC_NONE) {
       k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
@@ -768,7 +768,7 @@ template <class S> struct Ops {
     if (P->prec == ETC_MIXED) {
       if ((s = flush(P, false))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
-      if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
+      if ((s = fin(P, FIN_REFINE, residual_parts(P), residual_parts(P)))) return s;
     }
     k_norm2<S><<<lc.gridStride, kThreads, 0, P->stream>>>(g, r, P->partials, P->st);
     LAUNCHCHK("norm2");
@@ -804,7 +804,7 @@ template <class S> struct Ops {
       // residual when requested, and redo DCT_b
       if ((s = flush(P, true))) return s;
       if ((s = residual(P, r, P->st, 2))) return s;
-      if ((s = fin(P, FIN_REFINE, lc.nR, lc.nR))) return s;
+      if ((s = fin(P, FIN_REFINE, residual_parts(P), residual_parts(P)))) return s;
       rows_fwd<0>(P, r, t, nullptr, nullptr, nullptr, P->st, 2);
       LAUNCHCHK("rows_fwd_refine");
     }
@@ -855,19 +855,26 @@ template <class S> struct Ops {
     if (P->ortho)
       k_apply_A<S, S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
     else
-      k_apply_A_iso<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
+      k_apply_A_iso<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y,
+                                                                 partials, st, gate, lc.kchunk);
     LAUNCHCHK("apply_A");
     return ETC_OK;
   }
+
+  // partial sums the residual kernel writes per instance
+  static int residual_parts(const etc_plan* P) { return P->ortho ? P->lc.nR : P->lc.nA; }
 
   static etc_status residual(etc_plan* P, S* r, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     if (P->ortho)
       k_residual<S, true><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
                                                                    lc.kchunkR);
+    else if (P->kap_hi[0])  // float64 copy of a float64 input
+      k_apply_A_iso<S, true, double><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(
+          P->g, P->p, kap(P), P->kap_hi[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
     else
-      k_residual<S, false><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st,
-                                                                    gate, lc.kchunkR);
+      k_apply_A_iso<S, true, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(
+          P->g, P->p, kap(P), (const S*)P->kap_s[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
     LAUNCHCHK("residual");
     return ETC_OK;
   }

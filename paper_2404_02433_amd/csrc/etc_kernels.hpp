@@ -6,6 +6,8 @@
 // Every reduction writes one partial per block; a one-block finalize kernel
 // sums them in a fixed order, so results are bitwise reproducible.
 #pragma once
+#include <type_traits>
+
 #include "etc_common.hpp"
 #include "etc_fft.hpp"
 
@@ -389,11 +391,16 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
 // face is computed by its left voxel and passed on by a lane shift, and the
 // four faces left of a wave's first column by lanes 0..3.  Out-of-range
 // neighbours read finite defaults from LDS and get a zero coefficient.
-template <class S>
-__global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const S* __restrict__ w, Kap<S> kp, S* __restrict__ q,
-                                                     double* __restrict__ partials, const DevState* __restrict__ st,
-                                                     int gate, int kchunk) {
-  using C = S;
+//
+// RES = true: the float64 true residual r = b - A p of the mixed form (p
+// float64, kappa read as KT, arithmetic in C = double, r stored as S, partial
+// ||r||^2); RES = false: q = A w with the partial w . q, all in S.
+template <class S, bool RES = false, class KT = S>
+__global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
+                                                     Kap<S> kp, const KT* __restrict__ ks, Rhs rh,
+                                                     S* __restrict__ q, double* __restrict__ partials,
+                                                     const DevState* __restrict__ st, int gate, int kchunk) {
+  using C = typename std::conditional<RES, double, S>::type;
   const int ntile = gridDim.x * gridDim.y * gridDim.z;
   const int tile = xcd_tile(flat_block(), ntile);
   const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
@@ -405,7 +412,9 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const S* __restrict_
     const int64_t off = (int64_t)inst * g.V;
     w += off;
     q += off;
+    ks += off;
     kp.shift(off);
+    if (RES && rh.src) rh.src += off;
   }
   __shared__ C tw_[ATA + 2][ATB + 2];
   __shared__ C tk_[ATA + 2][ATB + 2];
@@ -415,7 +424,6 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const S* __restrict_
   const int b = b0 + tx;
   const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
-  const S* __restrict__ ks = kp.L;
   const C fL = (C)g.fL, fa = (C)g.fa, fb = (C)g.fb;
   const int64_t plane = g.plane;
   const bool bok = b < g.nb;
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const S* __restrict_
     hok = hr >= 0 && ha >= 0 && ha < g.na && hb >= 0 && hb < g.nb;
     if (hok) hcol = (int64_t)ha * g.nb + hb;
   }
-  auto ld = [&](const S* __restrict__ arr, int k, int64_t c, bool ok, C dflt) -> C {
+  auto ld = [&](const auto* __restrict__ arr, int k, int64_t c, bool ok, C dflt) -> C {
     return (ok && k >= 0 && k < g.nL) ? (C)arr[(int64_t)k * plane + c] : dflt;
   };
   // which faces exist
@@ -522,9 +530,16 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const S* __restrict_
       qv += fa * (fav[j] * (w0 - wa_) + fav[j + 1] * (w0 - wb_));
       qv += fb * (fl[j] * (w0 - tw_[r][cc - 1]) + fr[j] * (w0 - tw_[r][cc + 1]));
       if (rok[j]) {
-        const S qs = (S)qv;
-        q[(int64_t)k * plane + col[j]] = qs;
-        acc += (double)w0 * (double)qs;
+        const int64_t gi = (int64_t)k * plane + col[j];
+        if constexpr (RES) {
+          const S rs = (S)(rhs_at(g, kp, rh, gi, k, col[j]) - qv);
+          q[gi] = rs;
+          acc += (double)rs * (double)rs;
+        } else {
+          const S qs = (S)qv;
+          q[gi] = qs;
+          acc += (double)w0 * (double)qs;
+        }
       }
     }
 #pragma unroll
@@ -582,36 +597,43 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, const double* __restric
       pm = p[i - g.plane];
       km = kp.dL(i - g.plane);
     }
+    // load-axis face below the current plane (carried from plane to plane)
+    double tdn = (k0 > 0) ? hface(kc, km) : 2.0 * kc;
+    double pp = 0.0, kpp = 1.0;
+    if (k0 + 1 < g.nL) {
+      pp = p[i + g.plane];
+      kpp = kp.dL(i + g.plane);
+    }
     for (int k = k0; k < k1; ++k, i += g.plane) {
-      double pp = 0.0, kpp = 1.0;
-      if (k + 1 < g.nL) {
-        pp = p[i + g.plane];
-        kpp = kp.dL(i + g.plane);
+      // prefetch the plane after next
+      double pn = 0.0, kn = 1.0;
+      if (k + 2 < g.nL && k + 1 < k1) {
+        pn = p[i + 2 * g.plane];
+        kn = kp.dL(i + 2 * g.plane);
       }
-      double qv = 0.0;
-      if (k > 0) qv = g.fL * harm(kc, km) * (pc - pm);
-      else qv = 2.0 * g.fL * kc * pc;
-      if (k + 1 < g.nL) qv += g.fL * harm(kc, kpp) * (pc - pp);
-      else qv += 2.0 * g.fL * kc * pc;
+      const double tup = (k + 1 < g.nL) ? hface(kc, kpp) : 2.0 * kc;
+      double qv = g.fL * (tdn * (pc - pm) + tup * (pc - pp));
       const double kac = ORTHO ? kp.dA(i) : kc, kbc = ORTHO ? kp.dB(i) : kc;
       if (ORTHO) {
-        if (a > 0) qv += g.fa * harm(kac, kp.dA(i - g.nb)) * (pc - p[i - g.nb]);
-        if (a + 1 < g.na) qv += g.fa * harm(kac, kp.dA(i + g.nb)) * (pc - p[i + g.nb]);
-        if (b > 0) qv += g.fb * harm(kbc, kp.dB(i - 1)) * (pc - p[i - 1]);
-        if (b + 1 < g.nb) qv += g.fb * harm(kbc, kp.dB(i + 1)) * (pc - p[i + 1]);
+        if (a > 0) qv += g.fa * hface(kac, kp.dA(i - g.nb)) * (pc - p[i - g.nb]);
+        if (a + 1 < g.na) qv += g.fa * hface(kac, kp.dA(i + g.nb)) * (pc - p[i + g.nb]);
+        if (b > 0) qv += g.fb * hface(kbc, kp.dB(i - 1)) * (pc - p[i - 1]);
+        if (b + 1 < g.nb) qv += g.fb * hface(kbc, kp.dB(i + 1)) * (pc - p[i + 1]);
       } else {
-        if (a > 0) qv += g.fa * harm(kc, kp.dL(i - g.nb)) * (pc - p[i - g.nb]);
-        if (a + 1 < g.na) qv += g.fa * harm(kc, kp.dL(i + g.nb)) * (pc - p[i + g.nb]);
-        if (b > 0) qv += g.fb * harm(kc, kp.dL(i - 1)) * (pc - p[i - 1]);
-        if (b + 1 < g.nb) qv += g.fb * harm(kc, kp.dL(i + 1)) * (pc - p[i + 1]);
+        if (a > 0) qv += g.fa * hface(kc, kp.dL(i - g.nb)) * (pc - p[i - g.nb]);
+        if (a + 1 < g.na) qv += g.fa * hface(kc, kp.dL(i + g.nb)) * (pc - p[i + g.nb]);
+        if (b > 0) qv += g.fb * hface(kc, kp.dL(i - 1)) * (pc - p[i - 1]);
+        if (b + 1 < g.nb) qv += g.fb * hface(kc, kp.dL(i + 1)) * (pc - p[i + 1]);
       }
       const S rs = (S)(rhs_at(g, kp, rh, i, k, col) - qv);
       r[i] = rs;
       acc += (double)rs * (double)rs;
+      tdn = tup;
       pm = pc;
-      km = kc;
       pc = pp;
       kc = kpp;
+      pp = pn;
+      kpp = kn;
     }
   }
   const double s = block_sum(acc, red);
