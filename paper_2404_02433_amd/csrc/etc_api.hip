@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -560,18 +561,25 @@ template <class S> struct Ops {
     int kchunk, thomas_x;
   };
   static etc_status autotune(etc_plan* P) {
+    // shared by every plan of the process (plans may be set up from several threads)
+    static std::mutex mu;
     static std::vector<std::pair<std::vector<int64_t>, Tuned>> cache;
     LaunchCfg& lc = P->lc;
     const Geo& g = P->g;
-    const std::vector<int64_t> key = {g.nL, g.na, g.nb, P->nseg, (int64_t)sizeof(S), P->ortho ? 1 : 0,
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const std::vector<int64_t> key = {dev, g.nL, g.na, g.nb, P->nseg, (int64_t)sizeof(S), P->ortho ? 1 : 0,
                                       (int64_t)lc.gridThomas.x};
-    for (auto& e : cache)
-      if (e.first == key) {
-        set_stencil_chunk(lc, g, e.second.kchunk);
-        lc.gridThomas.x = e.second.thomas_x;
-        P->tuned = 1;
-        return ETC_OK;
-      }
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      for (auto& e : cache)
+        if (e.first == key) {
+          set_stencil_chunk(lc, g, e.second.kchunk);
+          lc.gridThomas.x = e.second.thomas_x;
+          P->tuned = 1;
+          return ETC_OK;
+        }
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -625,7 +633,10 @@ template <class S> struct Ops {
     (void)hipEventDestroy(e1);
     if (s) return s;
     HIPCHK(hipGetLastError());
-    cache.push_back({key, best});
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      cache.push_back({key, best});
+    }
     P->tuned = 1;
     return ETC_OK;
   }
