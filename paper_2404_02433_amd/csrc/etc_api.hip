@@ -202,7 +202,7 @@ void canonical_dims(const int64_t n[3], int axis, int& nL, int& na, int& nb) {
   nb = o[1];
 }
 
-// Stencil launch for planes chunks of `kchunk` (tiles of 64 b x 16 a).
+// Stencil launch for plane chunks of `kchunk` (tiles of 64 b x 16 a).
 void set_stencil_chunk(LaunchCfg& lc, const Geo& g, int kchunk) {
   const int gx = (g.nb + 63) / 64, gy = (g.na + 15) / 16;
   const int nch = (g.nL + kchunk - 1) / kchunk;

@@ -235,9 +235,8 @@ __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* 
 
 // ================================================================== operator
 // q = A w (7-point TPFA stencil, harmonic-mean faces recomputed from kappa)
-// with the partial w . q of each block.  Block (64, 4) covers 64 b x 4 a
-// columns and marches along k over `kchunk` planes keeping the k-1, k, k+1
-// values in registers; lateral neighbours come through the caches.
+// with the partial w . q of each block, for orthotropic kappa (the isotropic
+// operator is k_apply_A_iso below).
 // 2.5D tiling: a block of 64 x 4 threads owns a tile of 64 (b) x 16 (a)
 // columns (4 rows per thread) and marches along k over `kchunk` planes.  The
 // current plane of w and kappa sits in LDS with a one-voxel halo (lateral
@@ -561,7 +560,8 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const typename std::
 }
 
 // r = b - A p in double arithmetic (p double, kappa at its input precision),
-// stored at S precision, with the partial ||r||^2.  Columns of 64 b x 4 a
+// stored at S precision, with the partial ||r||^2, for orthotropic kappa (the
+// isotropic residual is k_apply_A_iso<S, true>).  Columns of 64 b x 4 a
 // march along k; lateral neighbours come through the caches (tiles
 // renumbered per XCD as in k_apply_A).
 template <class S, bool ORTHO>
