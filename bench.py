@@ -156,7 +156,7 @@ def ensemble_bench(torch, etc, rvegen, args):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     es = 4 if form == "mixed" else 8
-    it_bytes = sum(iteration_bytes_per_voxel(es, form == "mixed", 10) * k.size * it
+    it_bytes = sum(iteration_bytes_per_voxel(es, form == "mixed", 20) * k.size * it
                    for k, it in zip(kaps_np, out["iters"]))
     line = {
         "metric": "RVE ensemble throughput (64 mixed-size GRF RVEs to rel.res 1e-6)",
@@ -254,7 +254,7 @@ def main():
         dt, outs = time_form(torch, etc, kap, form, args.rtol, args.steps, args.warmup, args.kernel, args.autotune)
         o = outs[-1]
         es = 4 if form == "mixed" else 8
-        it_bytes = iteration_bytes_per_voxel(es, form == "mixed", 10) * V
+        it_bytes = iteration_bytes_per_voxel(es, form == "mixed", 20) * V
         kms = sum(x["kernel_ms"] for x in outs) / max(1, sum(x["kernel_launches"] for x in outs))
         res[form] = {"time_s": dt, "iters": o["iters"], "keff": o["keff"], "k_in": o["k_in"],
                      "relres": o["relres"], "status": o["status"],

@@ -83,7 +83,7 @@ typedef struct {
   double kref_user[5];   /* order: load-axis faces, a faces, b faces, in layer, out layer */
   double rtol;           /* default 1e-6 */
   int max_iter;          /* default 1000 */
-  int refine_every;      /* mixed form: true-residual period, default 10 */
+  int refine_every;      /* mixed form: true-residual period, default 20 */
   int poll_every;        /* passes enqueued between host checks, default 8 */
   void* stream;          /* hipStream_t; NULL = the null stream */
   double L[3];           /* domain length per user axis; all 0 = voxel edge 1 */

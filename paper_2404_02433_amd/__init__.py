@@ -167,7 +167,7 @@ def _torch():
     return torch
 
 
-def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=10, poll_every=8, kref="mid",
+def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=20, poll_every=8, kref="mid",
              kref_user=None, L=None, stream=None, want_grad=False, precond="dct", use_graph=False,
              autotune=False) -> _Options:
     lib = load_library()
@@ -241,7 +241,7 @@ class Plan:
 
 
 def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
-              rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
+              rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 20, poll_every: int = 8,
               kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, source=None,
               p_in_face=None, p_out_face=None, precond: str = "dct", use_graph: bool = False,
               autotune: bool = False) -> Plan:
@@ -304,7 +304,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
 
 
 def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
-                    rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 10, poll_every: int = 8,
+                    rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 20, poll_every: int = 8,
                     kref: str = "mid", kref_user=None, L=None, want_grad: bool = False,
                     precond: str = "dct", use_graph: bool = False, autotune: bool = False) -> Plan:
     """Batch of same-size RVEs: ``kappa`` has shape (B, n0, n1, n2)."""

@@ -912,7 +912,7 @@ void etc_options_default(etc_options* o) {
   for (int i = 0; i < 5; ++i) o->kref_user[i] = 1.0;
   o->rtol = 1e-6;
   o->max_iter = 1000;
-  o->refine_every = 10;
+  o->refine_every = 20;
   o->poll_every = 8;
   o->stream = nullptr;
   o->want_grad = 0;

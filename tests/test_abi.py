@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_defaults():
     assert "gfx950" in etc.etc_version()
     o = etc._options()
-    assert o.rtol == 1e-6 and o.max_iter == 1000 and o.refine_every == 10
+    assert o.rtol == 1e-6 and o.max_iter == 1000 and o.refine_every == 20
     assert o.precision == 0 and o.kref_mode == 0
 
 
