@@ -72,6 +72,13 @@ PRECOND_SHAPES = [
     (5, 96, 160),    # 96 -> M=48 (16x3); 160 -> M=80 (16x5)
     (64, 128, 34),   # 128 -> 16x4; 34 -> M=17 prime: O(N^2) route; nL=64: 32 partitions of 2
     (33, 16, 16),    # nL not a multiple of the partition length
+    (96, 8, 12),     # exact partitions of 3 rows
+    (128, 5, 7),     # exact partitions of 4 rows
+    (160, 6, 10),    # exact partitions of 5 rows
+    (256, 4, 16),    # exact partitions of 8 rows
+    (3, 256, 160),   # compile-time column length 256, row length 160
+    (2, 48, 512),    # compile-time column length 48, row length 512
+    (300, 3, 5),     # ragged partitions (no exact variant), 10 rows each
 ]
 
 
@@ -87,6 +94,20 @@ def test_preconditioner_matches_oracle_fp64(shape):
     err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
     assert err < 1e-11, err
     assert abs(rz - float(np.vdot(r, ref))) < 1e-10 * abs(float(np.vdot(r, ref)))
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", [(96, 8, 12), (256, 4, 16), (3, 256, 160), (2, 48, 512)])
+def test_preconditioner_mixed_shapes(shape):
+    """float32 storage, the same compile-time and exact-partition kernels."""
+    kap = lognormal(shape, seed=17 + sum(shape), sigma=0.7)
+    plan = etc.etc_setup(dev(kap, torch.float32), 0, precision="mixed")
+    pb = O.make_problem(kap.astype(np.float32).astype(np.float64), 0)
+    r = np.random.default_rng(9).standard_normal(pb.shape).astype(np.float32)
+    z = etc.etc_apply_Minv(plan, dev(r, torch.float32))
+    ref = O.apply_Aref_inv(r.astype(np.float64), O.kref_mid(pb))
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
     plan.close()
 
 
