@@ -74,14 +74,25 @@ __device__ __forceinline__ double rhs_at(const Geo& g, const Kap<S>& kp, const R
 template <class In, class S>
 __global__ void k_canon_rows(const In* __restrict__ src, S* __restrict__ dst, double* __restrict__ dst_hi, int axis,
                              Geo g) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    const int64_t k = i / g.plane, rem = i - k * g.plane;
-    const int64_t a = rem / g.nb, b = rem - a * g.nb;
-    const int64_t si = axis == 0 ? i : (a * g.nL + k) * g.nb + b;
-    const double v = (double)src[si];
-    dst[i] = (S)v;
-    if (dst_hi) dst_hi[i] = v;
+  if (axis == 0) {  // same layout: a converting copy
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+      const double v = (double)src[i];
+      dst[i] = (S)v;
+      if (dst_hi) dst_hi[i] = v;
+    }
+    return;
+  }
+  // rows (k, a) over the blocks, b over the threads
+  const int nrows = g.nL * g.na;
+  for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int k = row / g.na, a = row - k * g.na;
+    const int64_t di = (int64_t)row * g.nb, si = ((int64_t)a * g.nL + k) * g.nb;
+    for (int b = threadIdx.x; b < g.nb; b += blockDim.x) {
+      const double v = (double)src[si + b];
+      dst[di + b] = (S)v;
+      if (dst_hi) dst_hi[di + b] = v;
+    }
   }
 }
 
@@ -219,15 +230,20 @@ __global__ __launch_bounds__(256) void k_init(Geo g, double* __restrict__ p, S* 
     partials += (int64_t)blockIdx.y * gridDim.x;
   }
   double acc = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    const int64_t k = i / g.plane, col = i - k * g.plane;
-    const double bv = rhs_at(g, kp, rh, i, k, col);
-    p[i] = 0.0;
-    if (dlt) dlt[i] = S(0);
-    const S bs = (S)bv;
-    r[i] = bs;
-    acc += (double)bs * (double)bs;
+  // rows (k, a) over the blocks, b over the threads (one index split per row)
+  const int nrows = g.nL * g.na;
+  for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int k = row / g.na;
+    const int64_t r0 = (int64_t)row * g.nb, c0 = (int64_t)(row - k * g.na) * g.nb;
+    for (int b = threadIdx.x; b < g.nb; b += blockDim.x) {
+      const int64_t i = r0 + b;
+      const double bv = rhs_at(g, kp, rh, i, (int64_t)k, c0 + b);
+      p[i] = 0.0;
+      if (dlt) dlt[i] = S(0);
+      const S bs = (S)bv;
+      r[i] = bs;
+      acc += (double)bs * (double)bs;
+    }
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
