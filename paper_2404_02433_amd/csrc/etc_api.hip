@@ -38,6 +38,10 @@ etc_status fail(etc_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kThreads = 256;
+// isotropic stencil tile (b x a): 128 x 16 for float32 storage, 64 x 16 for
+// float64 (whose larger register footprint keeps the smaller block)
+constexpr int stencil_tbw(size_t elt) { return elt == 4 ? 128 : 64; }
+constexpr int kStencilTAH = 16;
 constexpr int kMaxGridStride = 2048;   // grid of the grid-stride reduction kernels
 constexpr int kThomasP = 32;           // partitions per line in the tridiagonal kernel
 constexpr int kThomasTB = 16;          // modes (lines) per tridiagonal block, float64 (128-byte rows)
@@ -49,6 +53,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // last dimension; nX is the number of blocks (= partial sums) per instance.
 struct LaunchCfg {
   // operator: block (64, 4) over 64 x 16 tiles; residual: 64 x 4 tiles
+  int stencilTBW;  // isotropic stencil tile width (b)
   dim3 gridA;
   int nA_max;  // partials of the stencil at its smallest chunk (autotuner candidates)
   int kchunk, nA;
@@ -204,20 +209,22 @@ void canonical_dims(const int64_t n[3], int axis, int& nL, int& na, int& nb) {
 
 // Stencil launch for plane chunks of `kchunk` (tiles of 64 b x 16 a).
 void set_stencil_chunk(LaunchCfg& lc, const Geo& g, int kchunk) {
-  const int gx = (g.nb + 63) / 64, gy = (g.na + 15) / 16;
+  const int tbw = lc.stencilTBW;
+  const int gx = (g.nb + tbw - 1) / tbw, gy = (g.na + kStencilTAH - 1) / kStencilTAH;
   const int nch = (g.nL + kchunk - 1) / kchunk;
   lc.kchunk = kchunk;
   lc.gridA = dim3(gx, gy, nch * g.nseg);
   lc.nA = gx * gy * nch;
 }
 
-LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt) {
+LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt, bool ortho) {
   LaunchCfg lc{};
   const size_t cx_sz = 2 * elt;
   const int ns = g.nseg;
-  // operator (tiles of 64 b x 16 a; the residual kernel keeps 64 x 4): aim for
-  // >= ~2048 blocks over the whole batch
-  const int gx = (g.nb + 63) / 64, gy = (g.na + 15) / 16;
+  // operator (tiles of stencil_tbw b x kStencilTAH a; the orthotropic
+  // kernels keep 64 x 16 and 64 x 4): aim for >= ~2048 blocks over the batch
+  lc.stencilTBW = ortho ? 64 : stencil_tbw(elt);
+  const int gx = (g.nb + lc.stencilTBW - 1) / lc.stencilTBW, gy = (g.na + kStencilTAH - 1) / kStencilTAH;
   const int64_t cols = (int64_t)gx * gy * ns;
   int kchunk = g.nL;
   while (kchunk > 16 && cols * ((g.nL + kchunk - 1) / kchunk) < 2048) kchunk = (kchunk + 1) / 2;
@@ -343,7 +350,7 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
   const int na = g.na, nb = g.nb;
   const size_t es = elt_size(o.precision);
   DctPlan dpa = make_dct_plan(na), dpb = make_dct_plan(nb);
-  LaunchCfg lc = make_launch(g, dpa, dpb, es);
+  LaunchCfg lc = make_launch(g, dpa, dpb, es, ps.ortho);
   Sizes s{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -866,7 +873,8 @@ template <class S> struct Ops {
     if (P->ortho)
       k_apply_A<S, S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
     else
-      k_apply_A_iso<S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y,
+      k_apply_A_iso<S, false, S, stencil_tbw(sizeof(S)), kStencilTAH>
+          <<<lc.gridA, dim3(stencil_tbw(sizeof(S)), kStencilTAH / 4), 0, P->stream>>>(P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y,
                                                                  partials, st, gate, lc.kchunk);
     LAUNCHCHK("apply_A");
     return ETC_OK;
@@ -881,10 +889,12 @@ template <class S> struct Ops {
       k_residual<S, true><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
                                                                    lc.kchunkR);
     else if (P->kap_hi[0])  // float64 copy of a float64 input
-      k_apply_A_iso<S, true, double><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(
+      k_apply_A_iso<S, true, double, stencil_tbw(sizeof(S)), kStencilTAH>
+          <<<lc.gridA, dim3(stencil_tbw(sizeof(S)), kStencilTAH / 4), 0, P->stream>>>(
           P->g, P->p, kap(P), P->kap_hi[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
     else
-      k_apply_A_iso<S, true, S><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(
+      k_apply_A_iso<S, true, S, stencil_tbw(sizeof(S)), kStencilTAH>
+          <<<lc.gridA, dim3(stencil_tbw(sizeof(S)), kStencilTAH / 4), 0, P->stream>>>(
           P->g, P->p, kap(P), (const S*)P->kap_s[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
     LAUNCHCHK("residual");
     return ETC_OK;
@@ -1030,7 +1040,7 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
   const size_t es = elt_size(P->prec);
   P->dpa = make_dct_plan(na);
   P->dpb = make_dct_plan(nb);
-  P->lc = make_launch(g, P->dpa, P->dpb, es);
+  P->lc = make_launch(g, P->dpa, P->dpb, es, ps.ortho);
   if (P->lc.gridCols.y > 65535 || P->lc.gridA.z > 65535) {
     delete P;
     return fail(ETC_E_UNSUPPORTED, "batch too large: load planes times instances exceeds 65535");

@@ -398,20 +398,20 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
   }
 }
 
-// Isotropic operator with every face coefficient computed once: block (64, 4)
-// owns the same 64 (b) x 16 (a) tiles as k_apply_A, but thread (x, y) holds the
+// Isotropic operator with every face coefficient computed once: block
+// (TBW, TAH / 4) owns a TBW (b) x TAH (a) tile, and thread (x, y) holds the
 // four consecutive rows a0 + 4y .. a0 + 4y + 3 of column b0 + x.  Load-axis
 // faces are carried from one plane to the next, the faces between a thread's
 // own rows are shared in registers (five a faces per four voxels), each b
 // face is computed by its left voxel and passed on by a lane shift, and the
-// four faces left of a wave's first column by lanes 0..3.  Out-of-range
+// four faces left of a wave's first column by its lanes 0..3.  Out-of-range
 // neighbours read finite defaults from LDS and get a zero coefficient.
 //
 // RES = true: the float64 true residual r = b - A p of the mixed form (p
 // float64, kappa read as KT, arithmetic in C = double, r stored as S, partial
 // ||r||^2); RES = false: q = A w with the partial w . q, all in S.
-template <class S, bool RES = false, class KT = S>
-__global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
+template <class S, bool RES, class KT, int TBW, int TAH>
+__global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso(Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
                                                      Kap<S> kp, const KT* __restrict__ ks, Rhs rh,
                                                      S* __restrict__ q, double* __restrict__ partials,
                                                      const DevState* __restrict__ st, int gate, int kchunk) {
@@ -431,11 +431,12 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const typename std::
     kp.shift(off);
     if (RES && rh.src) rh.src += off;
   }
-  __shared__ C tw_[ATA + 2][ATB + 2];
-  __shared__ C tk_[ATA + 2][ATB + 2];
+  static_assert(TAH % ARPT == 0 && TAH >= 16 && TBW >= TAH && TBW % 64 == 0, "tile shape");
+  __shared__ C tw_[TAH + 2][TBW + 2];
+  __shared__ C tk_[TAH + 2][TBW + 2];
   __shared__ double red[16];
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int b0 = bx * ATB, a0 = by * ATA;
+  const int b0 = bx * TBW, a0 = by * TAH;
   const int b = b0 + tx;
   const int k0 = chunk * kchunk;
   const int k1 = min(g.nL, k0 + kchunk);
@@ -460,8 +461,10 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const typename std::
   {
     int ha = -1, hb = -1;
     if (ty == 0) { ha = a0 - 1; hb = b; hr = 0; hc = tx + 1; }
-    else if (ty == 1) { ha = a0 + ATA; hb = b; hr = ATA + 1; hc = tx + 1; }
-    else if (tx < ATA) { ha = a0 + tx; hb = (ty == 2) ? b0 - 1 : b0 + ATB; hr = tx + 1; hc = (ty == 2) ? 0 : ATB + 1; }
+    else if (ty == 1) { ha = a0 + TAH; hb = b; hr = TAH + 1; hc = tx + 1; }
+    else if (ty <= 3 && tx < TAH) {
+      ha = a0 + tx; hb = (ty == 2) ? b0 - 1 : b0 + TBW; hr = tx + 1; hc = (ty == 2) ? 0 : TBW + 1;
+    }
     hok = hr >= 0 && ha >= 0 && ha < g.na && hb >= 0 && hb < g.nb;
     if (hok) hcol = (int64_t)ha * g.nb + hb;
   }
@@ -527,13 +530,14 @@ __global__ __launch_bounds__(256) void k_apply_A_iso(Geo g, const typename std::
     C fr[ARPT], fl[ARPT];
 #pragma unroll
     for (int j = 0; j < ARPT; ++j) fr[j] = br_ok ? hface(kc[j], tk_[rbase + j][cc + 1]) : C(0);
-    const int hl = tx & (ARPT - 1);
-    const C edge = hface(tk_[rbase + hl][0], tk_[rbase + hl][1]);
+    const int lane = tx & 63, cw = 1 + (tx - lane);  // LDS column of the wave's first lane
+    const int hl = lane & (ARPT - 1);
+    const C edge = hface(tk_[rbase + hl][cw - 1], tk_[rbase + hl][cw]);
 #pragma unroll
     for (int j = 0; j < ARPT; ++j) {
       const C up = __shfl_up(fr[j], 1, 64);
       const C e = __shfl(edge, j, 64);
-      fl[j] = bl_ok ? (tx == 0 ? e : up) : C(0);
+      fl[j] = bl_ok ? (lane == 0 ? e : up) : C(0);
     }
 #pragma unroll
     for (int j = 0; j < ARPT; ++j) {
