@@ -54,6 +54,8 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct LaunchCfg {
   // operator: block (64, 4) over 64 x 16 tiles; residual: 64 x 4 tiles
   int stencilTBW;  // isotropic stencil tile width (b)
+  dim3 gridRes;    // isotropic float64 residual (64-wide tiles), nRes blocks per instance
+  int nRes;
   dim3 gridA;
   int nA_max;  // partials of the stencil at its smallest chunk (autotuner candidates)
   int kchunk, nA;
@@ -215,6 +217,10 @@ void set_stencil_chunk(LaunchCfg& lc, const Geo& g, int kchunk) {
   lc.kchunk = kchunk;
   lc.gridA = dim3(gx, gy, nch * g.nseg);
   lc.nA = gx * gy * nch;
+  // the float64-arithmetic residual keeps 64-wide tiles (register footprint)
+  const int gx64 = (g.nb + 63) / 64;
+  lc.gridRes = dim3(gx64, gy, nch * g.nseg);
+  lc.nRes = gx64 * gy * nch;
 }
 
 LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt, bool ortho) {
@@ -228,11 +234,8 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   const int64_t cols = (int64_t)gx * gy * ns;
   int kchunk = g.nL;
   while (kchunk > 16 && cols * ((g.nL + kchunk - 1) / kchunk) < 2048) kchunk = (kchunk + 1) / 2;
-  const int nch = (g.nL + kchunk - 1) / kchunk;
-  lc.kchunk = kchunk;
-  lc.gridA = dim3(gx, gy, nch * ns);
-  lc.nA = gx * gy * nch;
-  lc.nA_max = gx * gy * ((g.nL + std::min(8, g.nL) - 1) / std::min(8, g.nL));
+  set_stencil_chunk(lc, g, kchunk);
+  lc.nA_max = ((g.nb + 63) / 64) * gy * ((g.nL + std::min(8, g.nL) - 1) / std::min(8, g.nL));
   {
     const int gy4 = (g.na + 3) / 4;
     int kc4 = g.nL;
@@ -881,7 +884,7 @@ template <class S> struct Ops {
   }
 
   // partial sums the residual kernel writes per instance
-  static int residual_parts(const etc_plan* P) { return P->ortho ? P->lc.nR : P->lc.nA; }
+  static int residual_parts(const etc_plan* P) { return P->ortho ? P->lc.nR : P->lc.nRes; }
 
   static etc_status residual(etc_plan* P, S* r, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
@@ -889,12 +892,12 @@ template <class S> struct Ops {
       k_residual<S, true><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
                                                                    lc.kchunkR);
     else if (P->kap_hi[0])  // float64 copy of a float64 input
-      k_apply_A_iso<S, true, double, stencil_tbw(sizeof(S)), kStencilTAH>
-          <<<lc.gridA, dim3(stencil_tbw(sizeof(S)), kStencilTAH / 4), 0, P->stream>>>(
+      k_apply_A_iso<S, true, double, 64, kStencilTAH>
+          <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
           P->g, P->p, kap(P), P->kap_hi[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
     else
-      k_apply_A_iso<S, true, S, stencil_tbw(sizeof(S)), kStencilTAH>
-          <<<lc.gridA, dim3(stencil_tbw(sizeof(S)), kStencilTAH / 4), 0, P->stream>>>(
+      k_apply_A_iso<S, true, S, 64, kStencilTAH>
+          <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
           P->g, P->p, kap(P), (const S*)P->kap_s[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
     LAUNCHCHK("residual");
     return ETC_OK;
