@@ -157,23 +157,35 @@ __global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __res
   }
   double bad = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool small = g.V < ((int64_t)1 << 31);  // 32-bit index splits
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    const int64_t k = i / g.plane, rem = i - k * g.plane;
-    const int64_t a = rem / g.nb, b = rem - a * g.nb;
+    int64_t k, a, b;
+    if (small) {
+      const uint32_t iu = (uint32_t)i, pl = (uint32_t)g.plane, nb = (uint32_t)g.nb;
+      const uint32_t k32 = iu / pl, rem = iu - k32 * pl, a32 = rem / nb;
+      k = k32;
+      a = a32;
+      b = rem - a32 * nb;
+    } else {
+      k = i / g.plane;
+      const int64_t rem = i - k * g.plane;
+      a = rem / g.nb;
+      b = rem - a * g.nb;
+    }
     const double kc = kp.dL(i), ka = kp.dA(i), kb = kp.dB(i);
     if (!(kc > 0.0) || !isfinite(kc) || !(ka > 0.0) || !isfinite(ka) || !(kb > 0.0) || !isfinite(kb)) bad += 1.0;
     if (k > 0) {
-      const double t = g.fL * harm(kc, kp.dL(i - g.plane));
+      const double t = g.fL * hface(kc, kp.dL(i - g.plane));
       mn[0] = fmin(mn[0], t);
       mx[0] = fmax(mx[0], t);
     }
     if (a > 0) {
-      const double t = g.fa * harm(ka, kp.dA(i - g.nb));
+      const double t = g.fa * hface(ka, kp.dA(i - g.nb));
       mn[1] = fmin(mn[1], t);
       mx[1] = fmax(mx[1], t);
     }
     if (b > 0) {
-      const double t = g.fb * harm(kb, kp.dB(i - 1));
+      const double t = g.fb * hface(kb, kp.dB(i - 1));
       mn[2] = fmin(mn[2], t);
       mx[2] = fmax(mx[2], t);
     }
