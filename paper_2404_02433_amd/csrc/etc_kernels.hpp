@@ -1241,14 +1241,6 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (PF && tile < ntiles) load(tile, cur, cur_s);
   for (; tile < ntiles; tile += gridDim.x) {
-    S nxt[PF ? MAXM : 1], nxt_s = S(0);
-    const int tn = tile + gridDim.x;
-    if (PF) {
-      if (tn < ntiles) load(tn, nxt, nxt_s);
-    } else {
-      load(tile, cur, cur_s);
-    }
-
     const int bm = (tile % ntx) * TB + l, am = tile / ntx;
     const bool line_ok = bm < g.nb;
     const bool active = line_ok && pok;
@@ -1256,6 +1248,19 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
     const int len = active ? lenp : 0;
     const double sft = line_ok ? (rm.lam_a[am] * kr[1] + rm.lam_b[bm] * kr[2]) : 0.0;
     const double Dint = sft + Dint0;
+    S nxt[PF ? MAXM : 1], nxt_s = S(0);
+    if constexpr (PF) {
+      // One counter tracks every vector load in order, so any wait issued
+      // after the prefetch (for the shift above or this tile's rows) would
+      // also wait for the whole prefetch: take both into registers first.
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) asm volatile("" ::"v"(cur[j]));
+      asm volatile("" ::"v"(cur_s), "v"(Dint));
+      const int tn = tile + gridDim.x;
+      if (tn < ntiles) load(tn, nxt, nxt_s);
+    } else {
+      load(tile, cur, cur_s);
+    }
     // register arrays are only ever indexed by unrolled constants
     double dv[MAXM], invu[MAXM];
     double quad = 0.0, ts = 0.0, y_last = 0.0, y_first = 0.0, m11 = 0.0, gj = 1.0;
