@@ -158,44 +158,66 @@ __global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __res
   double bad = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool small = g.V < ((int64_t)1 << 31);  // 32-bit index splits
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
-    int64_t k, a, b;
-    if (small) {
-      const uint32_t iu = (uint32_t)i, pl = (uint32_t)g.plane, nb = (uint32_t)g.nb;
-      const uint32_t k32 = iu / pl, rem = iu - k32 * pl, a32 = rem / nb;
-      k = k32;
-      a = a32;
-      b = rem - a32 * nb;
-    } else {
-      k = i / g.plane;
-      const int64_t rem = i - k * g.plane;
-      a = rem / g.nb;
-      b = rem - a * g.nb;
+  // UX voxels per thread and trip, all loads issued before any use
+  constexpr int UX = 4;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < g.V; i0 += UX * stride) {
+    int64_t kk[UX], aa[UX], bb[UX];
+    double kc[UX], ka[UX], kb[UX], nl[UX], na_[UX], nb_[UX];
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      const int64_t i = i0 + u * stride;
+      kk[u] = -1;
+      if (i < g.V) {
+        if (small) {
+          const uint32_t iu = (uint32_t)i, pl = (uint32_t)g.plane, nb = (uint32_t)g.nb;
+          const uint32_t k32 = iu / pl, rem = iu - k32 * pl, a32 = rem / nb;
+          kk[u] = k32;
+          aa[u] = a32;
+          bb[u] = rem - a32 * nb;
+        } else {
+          kk[u] = i / g.plane;
+          const int64_t rem = i - kk[u] * g.plane;
+          aa[u] = rem / g.nb;
+          bb[u] = rem - aa[u] * g.nb;
+        }
+        kc[u] = kp.dL(i);
+        ka[u] = kp.dA(i);
+        kb[u] = kp.dB(i);
+        nl[u] = kk[u] > 0 ? kp.dL(i - g.plane) : 1.0;
+        na_[u] = aa[u] > 0 ? kp.dA(i - g.nb) : 1.0;
+        nb_[u] = bb[u] > 0 ? kp.dB(i - 1) : 1.0;
+      }
     }
-    const double kc = kp.dL(i), ka = kp.dA(i), kb = kp.dB(i);
-    if (!(kc > 0.0) || !isfinite(kc) || !(ka > 0.0) || !isfinite(ka) || !(kb > 0.0) || !isfinite(kb)) bad += 1.0;
-    if (k > 0) {
-      const double t = g.fL * hface(kc, kp.dL(i - g.plane));
-      mn[0] = fmin(mn[0], t);
-      mx[0] = fmax(mx[0], t);
-    }
-    if (a > 0) {
-      const double t = g.fa * hface(ka, kp.dA(i - g.nb));
-      mn[1] = fmin(mn[1], t);
-      mx[1] = fmax(mx[1], t);
-    }
-    if (b > 0) {
-      const double t = g.fb * hface(kb, kp.dB(i - 1));
-      mn[2] = fmin(mn[2], t);
-      mx[2] = fmax(mx[2], t);
-    }
-    if (k == 0) {
-      mn[3] = fmin(mn[3], g.fL * kc);
-      mx[3] = fmax(mx[3], g.fL * kc);
-    }
-    if (k == g.nL - 1) {
-      mn[4] = fmin(mn[4], g.fL * kc);
-      mx[4] = fmax(mx[4], g.fL * kc);
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      if (kk[u] < 0) continue;
+      const int64_t k = kk[u];
+      if (!(kc[u] > 0.0) || !isfinite(kc[u]) || !(ka[u] > 0.0) || !isfinite(ka[u]) || !(kb[u] > 0.0) ||
+          !isfinite(kb[u]))
+        bad += 1.0;
+      if (k > 0) {
+        const double t = g.fL * hface(kc[u], nl[u]);
+        mn[0] = fmin(mn[0], t);
+        mx[0] = fmax(mx[0], t);
+      }
+      if (aa[u] > 0) {
+        const double t = g.fa * hface(ka[u], na_[u]);
+        mn[1] = fmin(mn[1], t);
+        mx[1] = fmax(mx[1], t);
+      }
+      if (bb[u] > 0) {
+        const double t = g.fb * hface(kb[u], nb_[u]);
+        mn[2] = fmin(mn[2], t);
+        mx[2] = fmax(mx[2], t);
+      }
+      if (k == 0) {
+        mn[3] = fmin(mn[3], g.fL * kc[u]);
+        mx[3] = fmax(mx[3], g.fL * kc[u]);
+      }
+      if (k == g.nL - 1) {
+        mn[4] = fmin(mn[4], g.fL * kc[u]);
+        mx[4] = fmax(mx[4], g.fL * kc[u]);
+      }
     }
   }
   __shared__ double red[12][4];
