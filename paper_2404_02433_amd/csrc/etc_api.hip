@@ -70,6 +70,7 @@ struct LaunchCfg {
   int tb, colThreads;
   dim3 gridCols;
   size_t ldsCols;
+  int colsPers;  // blocks of the persistent float32 column kernels (0: one block per tile)
   // tridiagonal
   dim3 gridThomas;  // persistent blocks per instance (x) times instances (z)
   int Puse, maxm, nThomas, thomasTiles;
@@ -486,6 +487,11 @@ template <class S> struct Ops {
       f(std::integral_constant<int, 0>{});
       with_ct_len<T, false>(P->dpa.N, P->lc.tb, f);
     }
+    with_cols_pf(P, [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      set((const void*)&k_cols_pf<S, T, -1, NC>, ColsPf<T, NC>::bytes);
+      set((const void*)&k_cols_pf<S, T, +1, NC>, ColsPf<T, NC>::bytes);
+    });
     if (rows > 65536) {
       auto f = [&](auto nc) {
         constexpr int NC = decltype(nc)::value;
@@ -524,10 +530,41 @@ template <class S> struct Ops {
                                                                                  lc.rpb, lc.nrows, x, st, gate);
     });
   }
+  // Calls f(std::integral_constant<int, NC>) when the plan's column
+  // transforms can run the persistent float32 kernel: one instance, a
+  // compile-time length, and the twiddles fitting beside two tiles per CU.
+  template <class F>
+  static void with_cols_pf(const etc_plan* P, F&& f) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (P->g.nseg != 1 || P->g.plane >= ((int64_t)1 << 31)) return;
+      with_ct_len<T, false>(P->dpa.N, P->lc.tb, [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        if constexpr (NC > 0) {
+          using Sh = DctShape<T, NC>;
+          if constexpr (Sh::col_threads == 512 && (Sh::cols * NC) % 512 == 0 && 512 % Sh::cols == 0 &&
+                        Sh::M % 2 == 0 && (Sh::cols * (Sh::M / 2)) % 512 == 0 &&
+                        2 * ColsPf<T, NC>::bytes <= 160 * 1024)
+            f(nc);
+        }
+      });
+    }
+  }
+
   template <int DIR>
   static void cols(etc_plan* P, S* t, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     const cx<T>* twa = (const cx<T>*)P->tw_a;
+    if (lc.colsPers > 0) {
+      bool done = false;
+      with_cols_pf(P, [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        const int ntx = (int)lc.gridCols.x, ntiles = (int)(lc.gridCols.x * lc.gridCols.y);
+        k_cols_pf<S, T, DIR, NC><<<lc.colsPers, 512, ColsPf<T, NC>::bytes, P->stream>>>(P->g, twa, t, ntx, ntiles,
+                                                                                       st, gate);
+        done = true;
+      });
+      if (done) return;
+    }
     with_ct_len<T, false>(P->dpa.N, lc.tb, [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       k_cols<S, T, DIR, NC><<<lc.gridCols, lc.colThreads, lc.ldsCols, P->stream>>>(P->g, P->dpa, twa, t, lc.tb, st,
@@ -648,6 +685,34 @@ template <class S> struct Ops {
       cache.push_back({key, best});
     }
     P->tuned = 1;
+    return ETC_OK;
+  }
+
+  // Persistent grid of the float32 column kernels: the blocks that fit on
+  // the device at once (both directions), at most one per tile.
+  static etc_status cols_grid(etc_plan* P) {
+    LaunchCfg& lc = P->lc;
+    lc.colsPers = 0;
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    hipError_t e = hipSuccess;
+    int occ = 0;
+    with_cols_pf(P, [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      int o1 = 0, o2 = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, (const void*)&k_cols_pf<S, T, -1, NC>, 512,
+                                                       ColsPf<T, NC>::bytes);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void*)&k_cols_pf<S, T, +1, NC>, 512,
+                                                         ColsPf<T, NC>::bytes);
+      occ = std::min(o1, o2);
+    });
+    if (e != hipSuccess) return fail(ETC_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    if (occ > 0) {
+      const int64_t ntiles = (int64_t)lc.gridCols.x * lc.gridCols.y;
+      lc.colsPers = (int)std::min<int64_t>(ntiles, (int64_t)cus * occ);
+    }
     return ETC_OK;
   }
 
@@ -1110,6 +1175,8 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
   s = (P->prec == ETC_MIXED) ? Ops<float>::lds_limits(P) : Ops<double>::lds_limits(P);
   if (s) return bail(s);
   s = (P->prec == ETC_MIXED) ? Ops<float>::thomas_grid(P) : Ops<double>::thomas_grid(P);
+  if (s) return bail(s);
+  s = (P->prec == ETC_MIXED) ? Ops<float>::cols_grid(P) : Ops<double>::cols_grid(P);
   if (s) return bail(s);
   P->tuned = 0;
   if (o.autotune) {

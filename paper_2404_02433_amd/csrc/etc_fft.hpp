@@ -292,7 +292,9 @@ __host__ __device__ constexpr int cols_tile(int M, int ls, int elt, bool fft) {
 
 // One radix-R Stockham stage over LINES lines of M points (line stride LS),
 // all shapes compile-time.  Same data flow as fft_stage.
-template <class T, int R, int DIR, int M, int NS, int LINES, int NTHR, int LS>
+// TWS: twiddle j of a stage is tw[TWS * j] (8 for the plan's table of 4N
+// entries, 1 for a table of its every 8th entry).
+template <class T, int R, int DIR, int M, int NS, int LINES, int NTHR, int LS, int TWS = 8>
 __device__ __forceinline__ void fft_stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
   constexpr int per_line = M / R;
   constexpr int items = LINES * per_line;
@@ -311,7 +313,7 @@ __device__ __forceinline__ void fft_stage_ct(cx<T>* buf, const cx<T>* __restrict
       if (NS > 1 && jm != 0) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> w = tw[8 * step * r * jm];
+          cx<T> w = tw[TWS * step * r * jm];
           if (DIR > 0) w.im = -w.im;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -335,14 +337,14 @@ __device__ __forceinline__ void fft_stage_ct(cx<T>* buf, const cx<T>* __restrict
   __syncthreads();
 }
 
-template <class T, int DIR, int M, int LINES, int NTHR, int LS, int S = 0, int NS = 1>
+template <class T, int DIR, int M, int LINES, int NTHR, int LS, int S = 0, int NS = 1, int TWS = 8>
 __device__ __forceinline__ void lds_fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
   constexpr RadixPlan rp = radix_plan(M);
   static_assert(rp.n > 0, "length not supported by the compile-time route");
   if constexpr (S < rp.n) {
     constexpr int R = rp.r[S];
-    fft_stage_ct<T, R, DIR, M, NS, LINES, NTHR, LS>(buf, tw, tid);
-    lds_fft_ct<T, DIR, M, LINES, NTHR, LS, S + 1, NS * R>(buf, tw, tid);
+    fft_stage_ct<T, R, DIR, M, NS, LINES, NTHR, LS, TWS>(buf, tw, tid);
+    lds_fft_ct<T, DIR, M, LINES, NTHR, LS, S + 1, NS * R, TWS>(buf, tw, tid);
   }
 }
 
@@ -355,9 +357,17 @@ __device__ __forceinline__ int vpos(int m) { return 2 * lpad(m >> 1) + (m & 1); 
 // Forward post-processing of one item k in [0, M/2]: from the half-length
 // spectrum Z (LDS line) produce the outputs X[k], X[N-k], X[M-k], X[M+k].
 // `emit(index, value)` stores one output.
+// W with X[k] = Re W, X[N-k] = -Im W, from A = Z[k] and B = Z[M-k].
+template <class T>
+__device__ __forceinline__ cx<T> dct_post_w(cx<T> A, cx<T> B, int k, const cx<T>* __restrict__ tw) {
+  const T half = T(0.5);
+  cx<T> s = cadd(A, cconj(B)), d = csub(A, cconj(B));
+  cx<T> V = csub(cscale(s, half), cscale(rot_i<+1>(cmul(tw[4 * k], d)), half));
+  return cmul(tw[k], V);
+}
+
 template <class T, class Emit>
 __device__ __forceinline__ void dct_post(const cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Emit emit) {
-  const T half = T(0.5);
   if (k == 0) {
     cx<T> z0 = Z[lpad(0)];
     emit(0, z0.re + z0.im);
@@ -368,18 +378,39 @@ __device__ __forceinline__ void dct_post(const cx<T>* Z, int k, int N, int M, co
   const int k2 = M - k;
   cx<T> A = Z[lpad(k)], B = Z[lpad(k2)];
   {
-    cx<T> s = cadd(A, cconj(B)), d = csub(A, cconj(B));
-    cx<T> V = csub(cscale(s, half), cscale(rot_i<+1>(cmul(tw[4 * k], d)), half));
-    cx<T> W = cmul(tw[k], V);
+    const cx<T> W = dct_post_w(A, B, k, tw);
     emit(k, W.re);
     emit(N - k, -W.im);
   }
   if (k2 != k) {
-    cx<T> s = cadd(B, cconj(A)), d = csub(B, cconj(A));
-    cx<T> V = csub(cscale(s, half), cscale(rot_i<+1>(cmul(tw[4 * k2], d)), half));
-    cx<T> W = cmul(tw[k2], V);
+    const cx<T> W = dct_post_w(B, A, k2, tw);
     emit(k2, W.re);
     emit(N - k2, -W.im);
+  }
+}
+
+// The same outputs in items of exactly four (M even): item 0 covers k = 0
+// and k = M/2, item k in [1, M/2) covers k and M - k.
+template <class T, class Emit>
+__device__ __forceinline__ void dct_post4(const cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Emit emit) {
+  if (k == 0) {
+    const cx<T> z0 = Z[lpad(0)];
+    emit(0, z0.re + z0.im);
+    emit(M, (z0.re - z0.im) * tw[M].re);
+    const int h = M / 2;
+    const cx<T> A = Z[lpad(h)];
+    const cx<T> W = dct_post_w(A, A, h, tw);
+    emit(h, W.re);
+    emit(N - h, -W.im);
+  } else {
+    const int k2 = M - k;
+    const cx<T> A = Z[lpad(k)], B = Z[lpad(k2)];
+    const cx<T> W = dct_post_w(A, B, k, tw);
+    emit(k, W.re);
+    emit(N - k, -W.im);
+    const cx<T> W2 = dct_post_w(B, A, k2, tw);
+    emit(k2, W2.re);
+    emit(N - k2, -W2.im);
   }
 }
 

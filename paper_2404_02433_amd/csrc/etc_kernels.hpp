@@ -1181,6 +1181,138 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   }
 }
 
+// Persistent float32 column transforms (compile-time lengths, one instance).
+// Block x takes tiles x, x + gridDim.x, ... and loads the next tile's inputs
+// into registers while the current one is transformed in LDS.  The loads of
+// a tile are only useful in flight if nothing after them forces a wait for
+// them: one counter tracks vector loads and stores in issue order, so every
+// tile issues the same number of global stores (a ragged tile repeats its
+// last column, whose duplicate lanes store the same values), the twiddles
+// come from LDS, and the forward outputs are grouped four to an item.  LDS:
+// the tile, every 8th twiddle (FFT stages) and the first 2N twiddles (DCT
+// pre/post steps).
+template <class T, int NC> struct ColsPf {
+  using Sh = DctShape<T, NC>;
+  static constexpr int tile_slots = Sh::cols * Sh::ls;
+  static constexpr int bytes = (tile_slots + Sh::M + 2 * NC) * 2 * (int)sizeof(T);
+};
+
+template <class S, class T, int DIR, int NC>
+__global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restrict__ tw, S* __restrict__ data,
+                                                    int ntx, int ntiles, const DevState* __restrict__ st, int gate) {
+  using Sh = DctShape<T, NC>;
+  static_assert(NC > 0 && sizeof(T) == 4 && Sh::col_threads == 512, "float32 compile-time lengths only");
+  constexpr int N = NC, M = Sh::M, LS = Sh::ls, TBV = Sh::cols, NTHR = Sh::col_threads;
+  constexpr int total = TBV * N;            // inputs (outputs) of a tile
+  constexpr int items = TBV * (M / 2 + 1);  // pre- (post-) processing items of a tile
+  static_assert(total % NTHR == 0 && NTHR % TBV == 0 && M % 2 == 0 && (TBV * (M / 2)) % NTHR == 0, "tile shape");
+  constexpr int UE = total / NTHR;
+  constexpr int UP = TBV * (M / 2) / NTHR;  // forward items of four outputs per thread
+  constexpr int UI = (items + NTHR - 1) / NTHR;
+  constexpr int NV = DIR < 0 ? UE : 4 * UI;
+  if (gated_out(st, gate)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* twc = buf + ColsPf<T, NC>::tile_slots;  // twc[j] = tw[8 j], j < M
+  cx<T>* twd = twc + M;                           // twd[j] = tw[j], j < 2N
+  int tid = threadIdx.x;
+  for (int j = tid; j < M; j += NTHR) twc[j] = tw[8 * j];
+  for (int j = tid; j < 2 * N; j += NTHR) twd[j] = tw[j];
+  __syncthreads();
+  uint32_t nb = (uint32_t)g.nb;
+
+  // tile -> first element and the last real column (offsets in a plane fit 32 bits)
+  auto locate = [&](int tile, S*& pl, int& last) {
+    const int bx = tile % ntx, plane = tile / ntx;
+    const int b0 = bx * TBV;
+    last = min(TBV, g.nb - b0) - 1;
+    pl = data + (int64_t)plane * g.plane + b0;
+  };
+  S x[NV];
+  auto load = [&](const S* pl, int last) {
+    const uint32_t c = (uint32_t)min(tid % TBV, last);
+    if constexpr (DIR < 0) {
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const uint32_t n = (uint32_t)(tid / TBV + u * (NTHR / TBV));
+        x[u] = pl[n * nb + c];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UI; ++u) {
+        const int e = tid + u * NTHR;
+        if (e < items) {
+          int i0, i1, i2, i3;
+          pre_inv_idx(e / TBV, N, M, i0, i1, i2, i3);
+          x[4 * u + 0] = pl[(uint32_t)i0 * nb + c];
+          x[4 * u + 1] = pl[(uint32_t)i1 * nb + c];
+          x[4 * u + 2] = pl[(uint32_t)i2 * nb + c];
+          x[4 * u + 3] = pl[(uint32_t)i3 * nb + c];
+        }
+      }
+    }
+  };
+
+  int tile = blockIdx.x;
+  S* pl = data;
+  int last = 0;
+  if (tile < ntiles) {
+    locate(tile, pl, last);
+    load(pl, last);
+  }
+  for (; tile < ntiles; tile += gridDim.x) {
+    // per-thread offsets are recomputed every tile rather than held in
+    // registers across the loop
+    asm volatile("" : "+v"(tid), "+s"(nb));
+    const int c = tid % TBV;
+    cx<T>* Lc = buf + c * LS;
+    // this tile's inputs -> LDS lines
+    if constexpr (DIR < 0) {
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const int n = tid / TBV + u * (NTHR / TBV);
+        reinterpret_cast<T*>(Lc)[vpos(dct_perm(n, N))] = (T)x[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UI; ++u) {
+        const int e = tid + u * NTHR;
+        if (e < items)
+          dct_pre_inv_vals(Lc, e / TBV, M, twd, (T)x[4 * u], (T)x[4 * u + 1], (T)x[4 * u + 2], (T)x[4 * u + 3]);
+      }
+    }
+    __syncthreads();
+    // the next tile's inputs -> registers, in flight during the transform
+    const int tn = tile + gridDim.x;
+    S* pln = pl;
+    int lastn = last;
+    if (tn < ntiles) {
+      locate(tn, pln, lastn);
+      load(pln, lastn);
+    }
+    lds_fft_ct<T, DIR, M, TBV, NTHR, LS, 0, 1, 1>(buf, twc, tid);
+    const uint32_t cg = (uint32_t)min(c, last);
+    if constexpr (DIR < 0) {
+      // items of exactly four outputs, stored straight from registers
+#pragma unroll
+      for (int u = 0; u < UP; ++u) {
+        const int k = tid / TBV + u * (NTHR / TBV);
+        dct_post4(Lc, k, N, M, twd, [&](int idx, T v) { pl[(uint32_t)idx * nb + cg] = (S)v; });
+      }
+    } else {
+      const T invM = T(1) / T(M);
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const int n = tid / TBV + u * (NTHR / TBV);
+        pl[(uint32_t)n * nb + cg] = (S)(reinterpret_cast<const T*>(Lc)[vpos(dct_perm(n, N))] * invM);
+      }
+    }
+    __syncthreads();  // the next tile rewrites the LDS lines
+    pl = pln;
+    last = lastn;
+  }
+}
+
 // =================================================================== Thomas
 
 // Solve T_{a',b'} z = t along k for every transverse mode (a', b'), in place,

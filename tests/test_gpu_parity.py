@@ -97,9 +97,11 @@ def test_preconditioner_matches_oracle_fp64(shape):
     plan.close()
 
 
-@pytest.mark.parametrize("shape", [(96, 8, 12), (256, 4, 16), (3, 256, 160), (2, 48, 512)])
+@pytest.mark.parametrize("shape", [(96, 8, 12), (256, 4, 16), (3, 256, 160), (2, 48, 512), (300, 3, 5), (64, 6, 40),
+                                   (33, 16, 16)])
 def test_preconditioner_mixed_shapes(shape):
-    """float32 storage, the same compile-time and exact-partition kernels."""
+    """float32 storage: compile-time (one-instance plans: persistent column)
+    kernels, exact and ragged tridiagonal partitions."""
     kap = lognormal(shape, seed=17 + sum(shape), sigma=0.7)
     plan = etc.etc_setup(dev(kap, torch.float32), 0, precision="mixed")
     pb = O.make_problem(kap.astype(np.float32).astype(np.float64), 0)
