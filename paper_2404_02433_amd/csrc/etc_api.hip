@@ -532,11 +532,12 @@ template <class S> struct Ops {
   }
   // Calls f(std::integral_constant<int, NC>) when the plan's column
   // transforms can run the persistent float32 kernel: one instance, a
-  // compile-time length, and the twiddles fitting beside two tiles per CU.
+  // compile-time length, whole tiles, and the twiddles fitting beside two
+  // tiles per CU.
   template <class F>
   static void with_cols_pf(const etc_plan* P, F&& f) {
     if constexpr (std::is_same<T, float>::value) {
-      if (P->g.nseg != 1 || P->g.plane >= ((int64_t)1 << 31)) return;
+      if (P->g.nseg != 1 || P->g.plane >= ((int64_t)1 << 31) || P->g.nb % P->lc.tb != 0) return;
       with_ct_len<T, false>(P->dpa.N, P->lc.tb, [&](auto nc) {
         constexpr int NC = decltype(nc)::value;
         if constexpr (NC > 0) {

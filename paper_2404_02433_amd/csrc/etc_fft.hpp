@@ -389,29 +389,19 @@ __device__ __forceinline__ void dct_post(const cx<T>* Z, int k, int N, int M, co
   }
 }
 
-// The same outputs in items of exactly four (M even): item 0 covers k = 0
-// and k = M/2, item k in [1, M/2) covers k and M - k.
+// The same outputs in items of exactly four (M even), without branches:
+// item 0 covers k = 0 and k = M/2, item k in [1, M/2) covers k and M - k.
 template <class T, class Emit>
 __device__ __forceinline__ void dct_post4(const cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Emit emit) {
-  if (k == 0) {
-    const cx<T> z0 = Z[lpad(0)];
-    emit(0, z0.re + z0.im);
-    emit(M, (z0.re - z0.im) * tw[M].re);
-    const int h = M / 2;
-    const cx<T> A = Z[lpad(h)];
-    const cx<T> W = dct_post_w(A, A, h, tw);
-    emit(h, W.re);
-    emit(N - h, -W.im);
-  } else {
-    const int k2 = M - k;
-    const cx<T> A = Z[lpad(k)], B = Z[lpad(k2)];
-    const cx<T> W = dct_post_w(A, B, k, tw);
-    emit(k, W.re);
-    emit(N - k, -W.im);
-    const cx<T> W2 = dct_post_w(B, A, k2, tw);
-    emit(k2, W2.re);
-    emit(N - k2, -W2.im);
-  }
+  const bool z = k == 0;
+  const int h = M / 2, k2 = z ? h : M - k;
+  const cx<T> A = Z[lpad(k)], B = Z[lpad(k2)];
+  const cx<T> W = dct_post_w(A, B, k, tw);               // k > 0: X[k], X[N-k]
+  const cx<T> W2 = dct_post_w(B, z ? B : A, k2, tw);     // X[k2], X[N-k2] (k = 0: X[M/2], X[N-M/2])
+  emit(k, z ? A.re + A.im : W.re);                       // k = 0: X[0]
+  emit(z ? M : N - k, z ? (A.re - A.im) * tw[M].re : -W.im);  // k = 0: X[M]
+  emit(k2, W2.re);
+  emit(N - k2, -W2.im);
 }
 
 // Backward pre-processing of one item k in [0, M/2] from the four inputs

@@ -1181,7 +1181,8 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   }
 }
 
-// Persistent float32 column transforms (compile-time lengths, one instance).
+// Persistent float32 column transforms (compile-time lengths, one instance,
+// whole tiles).
 // Block x takes tiles x, x + gridDim.x, ... and loads the next tile's inputs
 // into registers while the current one is transformed in LDS.  The loads of
 // a tile are only useful in flight if nothing after them forces a wait for
@@ -1209,7 +1210,10 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
   constexpr int UE = total / NTHR;
   constexpr int UP = TBV * (M / 2) / NTHR;  // forward items of four outputs per thread
   constexpr int UI = (items + NTHR - 1) / NTHR;
-  constexpr int NV = DIR < 0 ? UE : 4 * UI;
+  // forward inputs: 16-byte loads of four adjacent columns (whole tiles)
+  constexpr int CQ = TBV / 4, RPR = NTHR / CQ, UV = N / RPR;
+  static_assert(TBV % 4 == 0 && NTHR % CQ == 0 && N % RPR == 0, "forward load shape");
+  constexpr int NV = DIR < 0 ? 1 : 4 * UI;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -1229,14 +1233,13 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
     pl = data + (int64_t)plane * g.plane + b0;
   };
   S x[NV];
-  auto load = [&](const S* pl, int last) {
+  V16<S> xv[DIR < 0 ? UV : 1];
+  auto load = [&](const S* pl, int last, uint32_t nb) {
     const uint32_t c = (uint32_t)min(tid % TBV, last);
     if constexpr (DIR < 0) {
+      const uint32_t c4 = 4 * (uint32_t)(tid % CQ), r0 = (uint32_t)(tid / CQ);
 #pragma unroll
-      for (int u = 0; u < UE; ++u) {
-        const uint32_t n = (uint32_t)(tid / TBV + u * (NTHR / TBV));
-        x[u] = pl[n * nb + c];
-      }
+      for (int u = 0; u < UV; ++u) xv[u] = ld16(pl + (r0 + (uint32_t)(u * RPR)) * nb + c4);
     } else {
 #pragma unroll
       for (int u = 0; u < UI; ++u) {
@@ -1253,42 +1256,53 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
     }
   };
 
+  // inputs in registers -> LDS lines
+  auto stage = [&]() {
+    if constexpr (DIR < 0) {
+      const int c4 = 4 * (tid % CQ), r0 = tid / CQ;
+#pragma unroll
+      for (int u = 0; u < UV; ++u) {
+        const int pos = vpos(dct_perm(r0 + u * RPR, N));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) reinterpret_cast<T*>(buf + (c4 + j) * LS)[pos] = (T)xv[u].v[j];
+      }
+    } else {
+      const int c = tid % TBV;
+#pragma unroll
+      for (int u = 0; u < UI; ++u) {
+        const int e = tid + u * NTHR;
+        if (e < items)
+          dct_pre_inv_vals(buf + c * LS, e / TBV, M, twd, (T)x[4 * u], (T)x[4 * u + 1], (T)x[4 * u + 2],
+                           (T)x[4 * u + 3]);
+      }
+    }
+  };
+
+  // The first tile is staged before the loop; inside it the next tile's
+  // loads are issued before the transform and staged after the stores, so
+  // every wait for them leaves the stores of the tile in flight.
   int tile = blockIdx.x;
   S* pl = data;
   int last = 0;
   if (tile < ntiles) {
     locate(tile, pl, last);
-    load(pl, last);
+    load(pl, last, nb);
+    stage();
   }
+  __syncthreads();
   for (; tile < ntiles; tile += gridDim.x) {
     // per-thread offsets are recomputed every tile rather than held in
     // registers across the loop
     asm volatile("" : "+v"(tid), "+s"(nb));
     const int c = tid % TBV;
-    cx<T>* Lc = buf + c * LS;
-    // this tile's inputs -> LDS lines
-    if constexpr (DIR < 0) {
-#pragma unroll
-      for (int u = 0; u < UE; ++u) {
-        const int n = tid / TBV + u * (NTHR / TBV);
-        reinterpret_cast<T*>(Lc)[vpos(dct_perm(n, N))] = (T)x[u];
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < UI; ++u) {
-        const int e = tid + u * NTHR;
-        if (e < items)
-          dct_pre_inv_vals(Lc, e / TBV, M, twd, (T)x[4 * u], (T)x[4 * u + 1], (T)x[4 * u + 2], (T)x[4 * u + 3]);
-      }
-    }
-    __syncthreads();
+    const cx<T>* Lc = buf + c * LS;
     // the next tile's inputs -> registers, in flight during the transform
     const int tn = tile + gridDim.x;
-    S* pln = pl;
-    int lastn = last;
+    S* pln = data;
+    int lastn = 0;
     if (tn < ntiles) {
       locate(tn, pln, lastn);
-      load(pln, lastn);
+      load(pln, lastn, nb);
     }
     lds_fft_ct<T, DIR, M, TBV, NTHR, LS, 0, 1, 1>(buf, twc, tid);
     const uint32_t cg = (uint32_t)min(c, last);
@@ -1307,7 +1321,9 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
         pl[(uint32_t)n * nb + cg] = (S)(reinterpret_cast<const T*>(Lc)[vpos(dct_perm(n, N))] * invM);
       }
     }
-    __syncthreads();  // the next tile rewrites the LDS lines
+    __syncthreads();  // every read of this tile's LDS lines is done
+    if (tn < ntiles) stage();
+    __syncthreads();
     pl = pln;
     last = lastn;
   }
