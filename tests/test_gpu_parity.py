@@ -98,7 +98,7 @@ def test_preconditioner_matches_oracle_fp64(shape):
 
 
 @pytest.mark.parametrize("shape", [(96, 8, 12), (256, 4, 16), (3, 256, 160), (2, 48, 512), (300, 3, 5), (64, 6, 40),
-                                   (33, 16, 16)])
+                                   (33, 16, 16), (4, 128, 64), (5, 512, 32), (3, 512, 40), (2, 64, 160)])
 def test_preconditioner_mixed_shapes(shape):
     """float32 storage: compile-time (one-instance plans: persistent column)
     kernels, exact and ragged tridiagonal partitions."""
