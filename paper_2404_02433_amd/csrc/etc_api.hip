@@ -70,7 +70,7 @@ struct LaunchCfg {
   int tb, colThreads;
   dim3 gridCols;
   size_t ldsCols;
-  int colsPers;  // blocks of the persistent float32 column kernels (0: one block per tile)
+  int colsPers;  // blocks of the persistent column kernels (0: one block per tile)
   // tridiagonal
   dim3 gridThomas;  // persistent blocks per instance (x) times instances (z)
   int Puse, maxm, nThomas, thomasTiles;
@@ -531,24 +531,22 @@ template <class S> struct Ops {
     });
   }
   // Calls f(std::integral_constant<int, NC>) when the plan's column
-  // transforms can run the persistent float32 kernel: one instance, a
-  // compile-time length, whole tiles, and the twiddles fitting beside two
-  // tiles per CU.
+  // transforms can run the persistent kernel: one instance, a compile-time
+  // length, whole tiles, and the twiddles fitting beside two tiles per CU.
   template <class F>
   static void with_cols_pf(const etc_plan* P, F&& f) {
-    if constexpr (std::is_same<T, float>::value) {
-      if (P->g.nseg != 1 || P->g.plane >= ((int64_t)1 << 31) || P->g.nb % P->lc.tb != 0) return;
-      with_ct_len<T, false>(P->dpa.N, P->lc.tb, [&](auto nc) {
-        constexpr int NC = decltype(nc)::value;
-        if constexpr (NC > 0) {
-          using Sh = DctShape<T, NC>;
-          if constexpr (Sh::col_threads == 512 && (Sh::cols * NC) % 512 == 0 && 512 % Sh::cols == 0 &&
-                        Sh::M % 2 == 0 && (Sh::cols * (Sh::M / 2)) % 512 == 0 &&
-                        2 * ColsPf<T, NC>::bytes <= 160 * 1024)
-            f(nc);
-        }
-      });
-    }
+    if (P->g.nseg != 1 || P->g.plane >= ((int64_t)1 << 31) || P->g.nb % P->lc.tb != 0) return;
+    with_ct_len<T, false>(P->dpa.N, P->lc.tb, [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      if constexpr (NC > 0) {
+        using Sh = DctShape<T, NC>;
+        constexpr int NT = Sh::col_threads, VW = 16 / (int)sizeof(S);
+        if constexpr ((Sh::cols * NC) % NT == 0 && NT % Sh::cols == 0 && Sh::M % 2 == 0 &&
+                      (Sh::cols * (Sh::M / 2)) % NT == 0 && Sh::cols % VW == 0 &&
+                      NC % (NT / (Sh::cols / VW)) == 0 && 2 * ColsPf<T, NC>::bytes <= 160 * 1024)
+          f(nc);
+      }
+    });
   }
 
   template <int DIR>
@@ -560,8 +558,8 @@ template <class S> struct Ops {
       with_cols_pf(P, [&](auto nc) {
         constexpr int NC = decltype(nc)::value;
         const int ntx = (int)lc.gridCols.x, ntiles = (int)(lc.gridCols.x * lc.gridCols.y);
-        k_cols_pf<S, T, DIR, NC><<<lc.colsPers, 512, ColsPf<T, NC>::bytes, P->stream>>>(P->g, twa, t, ntx, ntiles,
-                                                                                       st, gate);
+        k_cols_pf<S, T, DIR, NC><<<lc.colsPers, lc.colThreads, ColsPf<T, NC>::bytes, P->stream>>>(
+            P->g, twa, t, ntx, ntiles, st, gate);
         done = true;
       });
       if (done) return;
@@ -689,7 +687,7 @@ template <class S> struct Ops {
     return ETC_OK;
   }
 
-  // Persistent grid of the float32 column kernels: the blocks that fit on
+  // Persistent grid of the column kernels: the blocks that fit on
   // the device at once (both directions), at most one per tile.
   static etc_status cols_grid(etc_plan* P) {
     LaunchCfg& lc = P->lc;
@@ -702,10 +700,10 @@ template <class S> struct Ops {
     with_cols_pf(P, [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       int o1 = 0, o2 = 0;
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, (const void*)&k_cols_pf<S, T, -1, NC>, 512,
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, (const void*)&k_cols_pf<S, T, -1, NC>, lc.colThreads,
                                                        ColsPf<T, NC>::bytes);
       if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void*)&k_cols_pf<S, T, +1, NC>, 512,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void*)&k_cols_pf<S, T, +1, NC>, lc.colThreads,
                                                          ColsPf<T, NC>::bytes);
       occ = std::min(o1, o2);
     });

@@ -357,9 +357,20 @@ __device__ __forceinline__ int vpos(int m) { return 2 * lpad(m >> 1) + (m & 1); 
 // Forward post-processing of one item k in [0, M/2]: from the half-length
 // spectrum Z (LDS line) produce the outputs X[k], X[N-k], X[M-k], X[M+k].
 // `emit(index, value)` stores one output.
-// W with X[k] = Re W, X[N-k] = -Im W, from A = Z[k] and B = Z[M-k].
-template <class T>
-__device__ __forceinline__ cx<T> dct_post_w(cx<T> A, cx<T> B, int k, const cx<T>* __restrict__ tw) {
+// Twiddles exp(-i pi j / 2N) of the DCT pre/post steps from two short
+// tables: j <= M (lo) and the multiples of 4 up to 4M (q, entry j / 4) --
+// every index those steps use.
+template <class T> struct DctTw {
+  const cx<T>* lo;
+  const cx<T>* q;
+  int M;
+  __device__ __forceinline__ cx<T> operator[](int j) const { return j <= M ? lo[j] : q[j >> 2]; }
+};
+
+// W with X[k] = Re W, X[N-k] = -Im W, from A = Z[k] and B = Z[M-k].  (TW:
+// a twiddle table pointer, or DctTw.)
+template <class T, class TW>
+__device__ __forceinline__ cx<T> dct_post_w(cx<T> A, cx<T> B, int k, const TW& tw) {
   const T half = T(0.5);
   cx<T> s = cadd(A, cconj(B)), d = csub(A, cconj(B));
   cx<T> V = csub(cscale(s, half), cscale(rot_i<+1>(cmul(tw[4 * k], d)), half));
@@ -391,8 +402,8 @@ __device__ __forceinline__ void dct_post(const cx<T>* Z, int k, int N, int M, co
 
 // The same outputs in items of exactly four (M even), without branches:
 // item 0 covers k = 0 and k = M/2, item k in [1, M/2) covers k and M - k.
-template <class T, class Emit>
-__device__ __forceinline__ void dct_post4(const cx<T>* Z, int k, int N, int M, const cx<T>* __restrict__ tw, Emit emit) {
+template <class T, class TW, class Emit>
+__device__ __forceinline__ void dct_post4(const cx<T>* Z, int k, int N, int M, const TW& tw, Emit emit) {
   const bool z = k == 0;
   const int h = M / 2, k2 = z ? h : M - k;
   const cx<T> A = Z[lpad(k)], B = Z[lpad(k2)];
@@ -407,9 +418,8 @@ __device__ __forceinline__ void dct_post4(const cx<T>* Z, int k, int N, int M, c
 // Backward pre-processing of one item k in [0, M/2] from the four inputs
 // xk = X[k], xnk = X[N-k], xk2 = X[M-k], xnk2 = X[M+k] (for k = 0: X[0], X[M]
 // in xk, xk2); writes Z[k] and Z[M-k] to the LDS line.
-template <class T>
-__device__ __forceinline__ void dct_pre_inv_vals(cx<T>* Z, int k, int M, const cx<T>* __restrict__ tw, T xk, T xnk,
-                                                 T xk2, T xnk2) {
+template <class T, class TW>
+__device__ __forceinline__ void dct_pre_inv_vals(cx<T>* Z, int k, int M, const TW& tw, T xk, T xnk, T xk2, T xnk2) {
   const T half = T(0.5);
   if (k == 0) {
     cx<T> V0 = {xk, T(0)};

@@ -1181,8 +1181,8 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   }
 }
 
-// Persistent float32 column transforms (compile-time lengths, one instance,
-// whole tiles).
+// Persistent column transforms (compile-time lengths, one instance, whole
+// tiles).
 // Block x takes tiles x, x + gridDim.x, ... and loads the next tile's inputs
 // into registers while the current one is transformed in LDS.  The loads of
 // a tile are only useful in flight if nothing after them forces a wait for
@@ -1190,19 +1190,19 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
 // tile issues the same number of global stores (a ragged tile repeats its
 // last column, whose duplicate lanes store the same values), the twiddles
 // come from LDS, and the forward outputs are grouped four to an item.  LDS:
-// the tile, every 8th twiddle (FFT stages) and the first 2N twiddles (DCT
-// pre/post steps).
+// the tile, every 8th twiddle (FFT stages) and the two short tables of the
+// DCT pre/post steps (DctTw).
 template <class T, int NC> struct ColsPf {
   using Sh = DctShape<T, NC>;
   static constexpr int tile_slots = Sh::cols * Sh::ls;
-  static constexpr int bytes = (tile_slots + Sh::M + 2 * NC) * 2 * (int)sizeof(T);
+  static constexpr int bytes = (tile_slots + Sh::M + 2 * (Sh::M + 1)) * 2 * (int)sizeof(T);
 };
 
 template <class S, class T, int DIR, int NC>
-__global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restrict__ tw, S* __restrict__ data,
+__global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::col_threads / 128)) void k_cols_pf(Geo g, const cx<T>* __restrict__ tw, S* __restrict__ data,
                                                     int ntx, int ntiles, const DevState* __restrict__ st, int gate) {
   using Sh = DctShape<T, NC>;
-  static_assert(NC > 0 && sizeof(T) == 4 && Sh::col_threads == 512, "float32 compile-time lengths only");
+  static_assert(NC > 0, "compile-time lengths only");
   constexpr int N = NC, M = Sh::M, LS = Sh::ls, TBV = Sh::cols, NTHR = Sh::col_threads;
   constexpr int total = TBV * N;            // inputs (outputs) of a tile
   constexpr int items = TBV * (M / 2 + 1);  // pre- (post-) processing items of a tile
@@ -1210,19 +1210,24 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
   constexpr int UE = total / NTHR;
   constexpr int UP = TBV * (M / 2) / NTHR;  // forward items of four outputs per thread
   constexpr int UI = (items + NTHR - 1) / NTHR;
-  // forward inputs: 16-byte loads of four adjacent columns (whole tiles)
-  constexpr int CQ = TBV / 4, RPR = NTHR / CQ, UV = N / RPR;
-  static_assert(TBV % 4 == 0 && NTHR % CQ == 0 && N % RPR == 0, "forward load shape");
+  // forward inputs: 16-byte loads of VW adjacent columns (whole tiles)
+  constexpr int VW = 16 / (int)sizeof(S), CQ = TBV / VW, RPR = NTHR / CQ, UV = N / RPR;
+  static_assert(TBV % VW == 0 && NTHR % CQ == 0 && N % RPR == 0, "forward load shape");
   constexpr int NV = DIR < 0 ? 1 : 4 * UI;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* twc = buf + ColsPf<T, NC>::tile_slots;  // twc[j] = tw[8 j], j < M
-  cx<T>* twd = twc + M;                           // twd[j] = tw[j], j < 2N
+  cx<T>* tlo = twc + M;                           // tlo[j] = tw[j], j <= M
+  cx<T>* tq = tlo + M + 1;                        // tq[j] = tw[4 j], j <= M
   int tid = threadIdx.x;
   for (int j = tid; j < M; j += NTHR) twc[j] = tw[8 * j];
-  for (int j = tid; j < 2 * N; j += NTHR) twd[j] = tw[j];
+  for (int j = tid; j <= M; j += NTHR) {
+    tlo[j] = tw[j];
+    tq[j] = tw[4 * j];
+  }
   __syncthreads();
+  const DctTw<T> twd{tlo, tq, M};
   uint32_t nb = (uint32_t)g.nb;
 
   // tile -> first element and the last real column (offsets in a plane fit 32 bits)
@@ -1237,7 +1242,7 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
   auto load = [&](const S* pl, int last, uint32_t nb) {
     const uint32_t c = (uint32_t)min(tid % TBV, last);
     if constexpr (DIR < 0) {
-      const uint32_t c4 = 4 * (uint32_t)(tid % CQ), r0 = (uint32_t)(tid / CQ);
+      const uint32_t c4 = VW * (uint32_t)(tid % CQ), r0 = (uint32_t)(tid / CQ);
 #pragma unroll
       for (int u = 0; u < UV; ++u) xv[u] = ld16(pl + (r0 + (uint32_t)(u * RPR)) * nb + c4);
     } else {
@@ -1259,12 +1264,12 @@ __global__ __launch_bounds__(512, 4) void k_cols_pf(Geo g, const cx<T>* __restri
   // inputs in registers -> LDS lines
   auto stage = [&]() {
     if constexpr (DIR < 0) {
-      const int c4 = 4 * (tid % CQ), r0 = tid / CQ;
+      const int c4 = VW * (tid % CQ), r0 = tid / CQ;
 #pragma unroll
       for (int u = 0; u < UV; ++u) {
         const int pos = vpos(dct_perm(r0 + u * RPR, N));
 #pragma unroll
-        for (int j = 0; j < 4; ++j) reinterpret_cast<T*>(buf + (c4 + j) * LS)[pos] = (T)xv[u].v[j];
+        for (int j = 0; j < VW; ++j) reinterpret_cast<T*>(buf + (c4 + j) * LS)[pos] = (T)xv[u].v[j];
       }
     } else {
       const int c = tid % TBV;
