@@ -119,6 +119,10 @@ struct etc_plan {
   std::vector<double> kref;    // 5 per instance (load-axis, a, b, in, out)
   double* kref_d;              // device copy
   std::vector<double> lam_lo, lam_hi;
+  // host copies of the uploaded tables (kept until the plan ends, so that
+  // their asynchronous uploads need no wait)
+  std::vector<double> lam_a_h, lam_b_h;
+  std::vector<unsigned char> tw_a_h, tw_b_h;
   bool solved;
   int last_iters;              // max over instances
   int last_status;             // worst over instances
@@ -1196,6 +1200,35 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
         hipStreamSynchronize(P->stream) != hipSuccess)
       return bail(fail(ETC_E_HIP, "copying the Dirichlet face data failed"));
   }
+  // tables (independent of kappa): built on the host while the device makes
+  // the canonical copy of the first instance, uploaded behind it
+  auto upload_tables = [&]() -> etc_status {
+    fill_lambda(P->lam_a_h, na);
+    fill_lambda(P->lam_b_h, nb);
+    if (P->prec == ETC_MIXED) {
+      std::vector<cx<float>> a, c;
+      fill_twiddles(a, na);
+      fill_twiddles(c, nb);
+      P->tw_a_h.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
+      P->tw_b_h.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
+    } else {
+      std::vector<cx<double>> a, c;
+      fill_twiddles(a, na);
+      fill_twiddles(c, nb);
+      P->tw_a_h.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
+      P->tw_b_h.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
+    }
+    if (hipMemcpyAsync(P->lam_a, P->lam_a_h.data(), na * sizeof(double), hipMemcpyHostToDevice, P->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->lam_b, P->lam_b_h.data(), nb * sizeof(double), hipMemcpyHostToDevice, P->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->tw_a, P->tw_a_h.data(), P->tw_a_h.size(), hipMemcpyHostToDevice, P->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->tw_b, P->tw_b_h.data(), P->tw_b_h.size(), hipMemcpyHostToDevice, P->stream) !=
+            hipSuccess)
+      return fail(ETC_E_HIP, "uploading the tables failed");
+    return ETC_OK;
+  };
   // canonical copies, extrema and reference parameters, instance by instance
   P->kref.assign((size_t)5 * nseg, 1.0);
   P->lam_lo.assign(nseg, 1.0);
@@ -1214,6 +1247,7 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
       s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source, inst)
                                  : Ops<double>::canon(P, comp, pr->source, inst);
       if (s) return bail(s);
+      if (inst == 0 && (s = upload_tables())) return bail(s);
       if (hipMemcpyAsync(part.data(), P->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost,
                          P->stream) != hipSuccess ||
           hipStreamSynchronize(P->stream) != hipSuccess)
@@ -1248,34 +1282,11 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
       P->lam_hi[inst] = hi;
     }
   }
-  // tables
-  {
-    std::vector<double> la, lb;
-    fill_lambda(la, na);
-    fill_lambda(lb, nb);
-    std::vector<unsigned char> twa, twb;
-    if (P->prec == ETC_MIXED) {
-      std::vector<cx<float>> a, c;
-      fill_twiddles(a, na);
-      fill_twiddles(c, nb);
-      twa.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
-      twb.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
-    } else {
-      std::vector<cx<double>> a, c;
-      fill_twiddles(a, na);
-      fill_twiddles(c, nb);
-      twa.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
-      twb.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
-    }
-    if (hipMemcpyAsync(P->lam_a, la.data(), na * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-        hipMemcpyAsync(P->lam_b, lb.data(), nb * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-        hipMemcpyAsync(P->tw_a, twa.data(), twa.size(), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-        hipMemcpyAsync(P->tw_b, twb.data(), twb.size(), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-        hipMemcpyAsync(P->kref_d, P->kref.data(), P->kref.size() * sizeof(double), hipMemcpyHostToDevice,
-                       P->stream) != hipSuccess ||
-        hipStreamSynchronize(P->stream) != hipSuccess)
-      return bail(fail(ETC_E_HIP, "uploading the tables failed"));
-  }
+  // reference parameters of every instance (no wait: the plan keeps the
+  // host copy, and etc_destroy synchronises before releasing it)
+  if (hipMemcpyAsync(P->kref_d, P->kref.data(), P->kref.size() * sizeof(double), hipMemcpyHostToDevice,
+                     P->stream) != hipSuccess)
+    return bail(fail(ETC_E_HIP, "uploading the reference parameters failed"));
   P->solved = false;
   *out = P;
   return ETC_OK;
