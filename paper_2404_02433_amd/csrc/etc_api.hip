@@ -119,6 +119,7 @@ struct etc_plan {
   std::vector<double> kref;    // 5 per instance (load-axis, a, b, in, out)
   double* kref_d;              // device copy
   std::vector<double> lam_lo, lam_hi;
+  bool any_done;  // some instance had converged at the last poll (batch plans)
   // host copies of the uploaded tables (kept until the plan ends, so that
   // their asynchronous uploads need no wait)
   std::vector<double> lam_a_h, lam_b_h;
@@ -535,11 +536,11 @@ template <class S> struct Ops {
     });
   }
   // Calls f(std::integral_constant<int, NC>) when the plan's column
-  // transforms can run the persistent kernel: one instance, a compile-time
-  // length, whole tiles, and the twiddles fitting beside two tiles per CU.
+  // transforms can run the persistent kernel: a compile-time length, whole
+  // tiles, and the twiddles fitting beside two tiles per CU.
   template <class F>
   static void with_cols_pf(const etc_plan* P, F&& f) {
-    if (P->g.nseg != 1 || P->g.plane >= ((int64_t)1 << 31) || P->g.nb % P->lc.tb != 0) return;
+    if (P->g.plane >= ((int64_t)1 << 31) || P->g.nb % P->lc.tb != 0) return;
     with_ct_len<T, false>(P->dpa.N, P->lc.tb, [&](auto nc) {
       constexpr int NC = decltype(nc)::value;
       if constexpr (NC > 0) {
@@ -557,13 +558,20 @@ template <class S> struct Ops {
   static void cols(etc_plan* P, S* t, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     const cx<T>* twa = (const cx<T>*)P->tw_a;
-    if (lc.colsPers > 0) {
+    // A batch runs the persistent kernel only while no instance had
+    // converged at the last poll, and without its exit test: it cannot skip
+    // the tiles of one instance and keep the same stores per tile, and
+    // transforming the scratch rows of an instance that has just converged
+    // changes nothing it still uses.  Refinement-only launches keep the
+    // gated kernel.
+    const bool single = P->g.nseg == 1;
+    if (lc.colsPers > 0 && (single || (gate <= 1 && !P->any_done))) {
       bool done = false;
       with_cols_pf(P, [&](auto nc) {
         constexpr int NC = decltype(nc)::value;
         const int ntx = (int)lc.gridCols.x, ntiles = (int)(lc.gridCols.x * lc.gridCols.y);
         k_cols_pf<S, T, DIR, NC><<<lc.colsPers, lc.colThreads, ColsPf<T, NC>::bytes, P->stream>>>(
-            P->g, twa, t, ntx, ntiles, st, gate);
+            P->g, twa, t, ntx, ntiles, single ? st : nullptr, single ? gate : 0);
         done = true;
       });
       if (done) return;
@@ -1299,6 +1307,7 @@ static etc_status reset_state(etc_plan* P) {
   h.refine_every = (P->prec == ETC_MIXED) ? std::max(0, P->opt.refine_every) : 0;
   h.mixed = (P->prec == ETC_MIXED) ? 1 : 0;
   for (int i = 0; i < P->nseg; ++i) P->st_host[i] = h;
+  P->any_done = false;
   HIPCHK(hipMemcpyAsync(P->st, P->st_host, sizeof(DevState) * P->nseg, hipMemcpyHostToDevice, P->stream));
   return ETC_OK;
 }
@@ -1406,6 +1415,7 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
     if ((s = pull_state(P))) return s;
     bool all_done = true;
     for (int i = 0; i < P->nseg; ++i) all_done = all_done && P->st_host[i].done;
+    for (int i = 0; i < P->nseg; ++i) P->any_done = P->any_done || P->st_host[i].done;
     if (all_done || enq > P->opt.max_iter) break;
     if (exec) {
       HIPCHK(hipGraphLaunch(exec, gstream));

@@ -1181,8 +1181,8 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
   }
 }
 
-// Persistent column transforms (compile-time lengths, one instance, whole
-// tiles).
+// Persistent column transforms (compile-time lengths, whole tiles; a batch
+// runs them without the per-instance exit test).
 // Block x takes tiles x, x + gridDim.x, ... and loads the next tile's inputs
 // into registers while the current one is transformed in LDS.  The loads of
 // a tile are only useful in flight if nothing after them forces a wait for
