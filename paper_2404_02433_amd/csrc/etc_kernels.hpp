@@ -1187,15 +1187,19 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
 // into registers while the current one is transformed in LDS.  The loads of
 // a tile are only useful in flight if nothing after them forces a wait for
 // them: one counter tracks vector loads and stores in issue order, so every
-// tile issues the same number of global stores (a ragged tile repeats its
-// last column, whose duplicate lanes store the same values), the twiddles
-// come from LDS, and the forward outputs are grouped four to an item.  LDS:
-// the tile, every 8th twiddle (FFT stages) and the two short tables of the
-// DCT pre/post steps (DctTw).
+// tile issues the same number of global stores (the host runs these kernels
+// on whole tiles only; the column clamp below would make a ragged tile's
+// extra lanes repeat its last column), the twiddles come from LDS, and the
+// forward outputs are grouped four to an item.  LDS:
+// the tile, every 8th twiddle (FFT stages) and the twiddles of the DCT
+// pre/post steps (float32: the first 2N; float64: the two short tables of
+// DctTw, which keep two tiles per CU).
 template <class T, int NC> struct ColsPf {
   using Sh = DctShape<T, NC>;
+  static constexpr bool full = sizeof(T) == 4;
   static constexpr int tile_slots = Sh::cols * Sh::ls;
-  static constexpr int bytes = (tile_slots + Sh::M + 2 * (Sh::M + 1)) * 2 * (int)sizeof(T);
+  static constexpr int dct_slots = full ? 2 * NC : 2 * (Sh::M + 1);
+  static constexpr int bytes = (tile_slots + Sh::M + dct_slots) * 2 * (int)sizeof(T);
 };
 
 template <class S, class T, int DIR, int NC>
@@ -1218,16 +1222,23 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* twc = buf + ColsPf<T, NC>::tile_slots;  // twc[j] = tw[8 j], j < M
-  cx<T>* tlo = twc + M;                           // tlo[j] = tw[j], j <= M
-  cx<T>* tq = tlo + M + 1;                        // tq[j] = tw[4 j], j <= M
+  cx<T>* tlo = twc + M;                           // tlo[j] = tw[j], j < 2N (float32) or j <= M
+  cx<T>* tq = tlo + M + 1;                        // (float64) tq[j] = tw[4 j], j <= M
   int tid = threadIdx.x;
   for (int j = tid; j < M; j += NTHR) twc[j] = tw[8 * j];
-  for (int j = tid; j <= M; j += NTHR) {
-    tlo[j] = tw[j];
-    tq[j] = tw[4 * j];
+  if constexpr (ColsPf<T, NC>::full) {
+    for (int j = tid; j < 2 * N; j += NTHR) tlo[j] = tw[j];
+  } else {
+    for (int j = tid; j <= M; j += NTHR) {
+      tlo[j] = tw[j];
+      tq[j] = tw[4 * j];
+    }
   }
   __syncthreads();
-  const DctTw<T> twd{tlo, tq, M};
+  using TwD = typename std::conditional<ColsPf<T, NC>::full, const cx<T>*, DctTw<T>>::type;
+  TwD twd;
+  if constexpr (ColsPf<T, NC>::full) twd = tlo;
+  else twd = DctTw<T>{tlo, tq, M};
   uint32_t nb = (uint32_t)g.nb;
 
   // tile -> first element and the last real column (offsets in a plane fit 32 bits)
