@@ -422,6 +422,27 @@ def test_batch_matches_individual_solves(precision):
             assert out["keff"][i] == single["keff"]   # same reductions, same order
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_with_persistent_column_kernels(precision):
+    """A batch whose column length has compile-time kernels (64) and whole
+    column tiles runs the persistent column kernels until an instance
+    converges, then the gated ones: every instance still reaches its own
+    solve's K_eff and the oracle's."""
+    shape = (16, 64, 64)
+    kaps = [np.exp(s * np.random.default_rng(300 + i).standard_normal(shape)) for i, s in enumerate([0.1, 0.8, 1.5])]
+    rtol = 1e-10 if precision == "fp64" else 1e-6
+    out = etc.solve_batch(dev(np.stack(kaps)), 0, precision=precision, rtol=rtol)
+    assert all(st == "ok" for st in out["status"])
+    assert len(set(out["iters"])) > 1
+    for i, k in enumerate(kaps):
+        ref = O.solve(k, 0, rtol=1e-12)
+        tol = 1e-8 if precision == "fp64" else 1e-5
+        assert abs(out["keff"][i] - ref["keff"]) <= tol * ref["keff"], (i, out["keff"][i], ref["keff"])
+        single = etc.solve(dev(k), 0, precision=precision, rtol=rtol)
+        assert abs(out["iters"][i] - single["iters"]) <= 1
+        assert abs(out["keff"][i] - single["keff"]) <= tol * ref["keff"]
+
+
 def test_batch_solution_and_gradient_layout():
     n = (10, 12, 14)
     kaps = np.stack([np.exp(0.5 * np.random.default_rng(7 + i).standard_normal(n)) for i in range(3)])
