@@ -92,3 +92,16 @@ def test_state_errors_on_null_plan():
     assert lib.etc_solve(None, None, None) == -1
     assert lib.etc_set_kernel_timer(None, 1) == -1
     lib.etc_destroy(None)  # no-op
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits
+    before touching a device."""
+    import json
+    import subprocess
+    import sys
+
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
