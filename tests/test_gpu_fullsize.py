@@ -55,8 +55,8 @@ def bounds(kap):
 
 
 @pytest.fixture(scope="module")
-def spheres512():
-    kap, info = rvegen.make_config("spheres512")
+def spheres512(rve_inputs):
+    kap, info = rve_inputs("spheres512")
     return kap
 
 
@@ -125,53 +125,105 @@ def test_spheres512_solves_bench_configuration(spheres512):
 
 def test_center_ball_512_reproduces_table2():
     """Table 2 prints K_eff of the center-ball RVE at 512^3 (load along z) to
-    three decimals; the float64 solve must round to the printed values."""
+    three decimals; the float64 solve must round to the printed values
+    (|K - printed| <= 5e-4)."""
     with open(os.path.join(GOLD, "table2_center_ball.json")) as f:
         t2 = json.load(f)
     for kinc, kpaper in zip(t2["kappa_inc"], t2["keff"]):
         kap = rvegen.center_ball(512, kinc)
         res = etc.solve(dev(kap), 2, rtol=1e-6)
         assert res["status"] == "ok"
-        assert abs(res["keff"] - kpaper) <= 1e-3, (kinc, res["keff"], kpaper)
+        assert abs(res["keff"] - kpaper) <= 5e-4, (kinc, res["keff"], kpaper)
 
 
 # ---------------------------------------------------------- 128^3 spheroids
-def test_spheroids128_matches_oracle_solve():
-    kap, _ = rvegen.make_config("spheroids128")
+def test_spheroids128_matches_oracle_solve(rve_inputs):
+    """A whole oracle solve at rtol 1e-8 (load x) against the float64 form
+    at the same rtol: same pass count within one, K within 1e-8.  (All three
+    loads against the oracle at rtol 1e-6 and 1e-10 are in the golden K_eff
+    tests.)"""
+    kap, _ = rve_inputs("spheroids128")
     ref = O.solve(kap, 0, rtol=1e-8)
     k64 = etc.solve(dev(kap), 0, rtol=1e-8)
     assert abs(k64["keff"] - ref["keff"]) <= 1e-8 * ref["keff"]
     assert abs(k64["iters"] - ref["pcg"].iters) <= 1
     lo, hi = bounds(kap)
-    for axis in (0, 1, 2):
-        kf = etc.solve(dev(kap), axis, rtol=1e-6)["keff"]
-        km = etc.solve(dev(kap), axis, rtol=1e-6, precision="mixed")["keff"]
-        assert lo <= kf <= hi
-        assert abs(km - kf) <= 1e-5 * kf
-    # the fibres are randomly oriented: the three loads give close K
-    assert abs(etc.solve(dev(kap), 0)["keff"] - ref["keff"]) <= 1e-5 * ref["keff"]
+    assert lo <= k64["keff"] <= hi
 
 
 # ------------------------------------------------------------- 256^3 GRF
-def test_grf256_gradient_by_finite_differences():
-    """dK/dkappa at 256^3 against central differences of the energy form of K
-    (whose error is quadratic in the solution error) at sampled voxels."""
+GOLD_KEFF = os.path.join(GOLD, "oracle_keff.json")
+
+
+def grf256_golden():
+    if not os.path.exists(GOLD_KEFF):
+        return None
+    with open(GOLD_KEFF) as f:
+        return json.load(f).get("grf256")
+
+
+@pytest.fixture(scope="module")
+def grf256_gradient():
+    """The 256^3 log-normal RVE as stored (float32) and its float64-form
+    adjoint gradient at rtol 1e-12."""
     kap, _ = rvegen.make_config("grf256")
-    kap = kap.astype(np.float64)
-    plan = etc.etc_setup(dev(kap), 0, rtol=1e-12, want_grad=True)
-    etc.etc_solve(plan)
+    assert kap.dtype == np.float32
+    plan = etc.etc_setup(dev(kap, torch.float32), 0, rtol=1e-12, want_grad=True)
+    out = etc.etc_solve(plan)
+    assert out["status"] == "ok"
     g = etc.etc_grad(plan).cpu().numpy()
     plan.close()
+    return kap, g
+
+
+def test_grf256_gradient_matches_oracle_samples(grf256_gradient):
+    """dK_xx/dkappa (float32 input, float64 form) against the oracle's
+    energy-form gradient at its solution, at the 64 stored voxels."""
+    gold = grf256_golden()
+    if gold is None or "grad_samples" not in gold:
+        pytest.skip("no oracle gradient samples for grf256")
+    kap, g = grf256_gradient
+    gs = gold["grad_samples"]
+    idx = np.array(gs["idx"])
+    got = g[tuple(idx.T)]
+    ref = np.array(gs["values"])
+    assert np.abs(got - ref).max() <= 1e-8 * gs["max_abs"], np.abs(got - ref).max() / gs["max_abs"]
+    assert abs(np.abs(g).max() - gs["max_abs"]) <= 1e-8 * gs["max_abs"]
+
+
+@pytest.mark.parametrize("part", [0, 1])
+def test_grf256_gradient_by_finite_differences(grf256_gradient, part):
+    """dK_xx/dkappa at 64 seeded voxels (seed 33; 32 per part) against
+    central differences of the energy form of K (error quadratic in the
+    solution error), each side solved to rtol 1e-12 in float64 on the
+    float32 input perturbed by +-1 % at the voxel."""
+    kap, g = grf256_gradient
     rng = np.random.default_rng(33)
-    idx = [tuple(int(rng.integers(0, s)) for s in kap.shape) for _ in range(6)]
-    idx.append((0, 100, 100))
-    idx.append((kap.shape[0] - 1, 30, 200))
-    for v in idx:
-        d = 1e-2 * kap[v]
+    # the same 64 voxels as the oracle's stored gradient samples
+    idx = [tuple(int(c) for c in row) for row in np.stack([rng.integers(0, s, 64) for s in kap.shape], axis=1)]
+    x = dev(kap, torch.float32)
+    gmax = np.abs(g).max()
+    for v in idx[32 * part:32 * (part + 1)]:
+        k0 = x[v].item()
+        kp, km = np.float32(k0 * 1.01), np.float32(k0 * 0.99)
         ks = []
-        for sgn in (1, -1):
-            kk = kap.copy()
-            kk[v] += sgn * d
-            ks.append(etc.solve(dev(kk), 0, rtol=1e-12, energy=True)["k_energy"])
-        fd = (ks[0] - ks[1]) / (2 * d)
-        assert abs(fd - g[v]) <= 1e-4 * abs(g[v]) + 1e-9 * np.abs(g).max(), (v, fd, g[v])
+        for kv in (kp, km):
+            x[v] = float(kv)
+            ks.append(etc.solve(x, 0, rtol=1e-12, energy=True)["k_energy"])
+        x[v] = k0
+        fd = (ks[0] - ks[1]) / (float(kp) - float(km))
+        assert abs(fd - g[v]) <= 1e-4 * abs(g[v]) + 1e-9 * gmax, (v, fd, g[v])
+
+
+def test_grf256_mixed_gradient_against_float64(grf256_gradient):
+    """The mixed form's gradient (float32 storage, primal and adjoint solves
+    to rtol 1e-6) against the float64 form's at rtol 1e-12: the largest
+    difference relative to the largest entry."""
+    kap, g = grf256_gradient
+    plan = etc.etc_setup(dev(kap, torch.float32), 0, precision="mixed", rtol=1e-6, want_grad=True)
+    assert etc.etc_solve(plan)["status"] == "ok"
+    gm = etc.etc_grad(plan).cpu().numpy()
+    plan.close()
+    err = np.abs(gm - g).max() / np.abs(g).max()
+    print(f"grf256 mixed gradient: max |g_mixed - g_f64| / max |g_f64| = {err:.3e}", flush=True)
+    assert err <= 2e-4, err
