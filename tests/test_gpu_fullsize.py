@@ -217,13 +217,21 @@ def test_grf256_gradient_by_finite_differences(grf256_gradient, part):
 
 def test_grf256_mixed_gradient_against_float64(grf256_gradient):
     """The mixed form's gradient (float32 storage, primal and adjoint solves
-    to rtol 1e-6) against the float64 form's at rtol 1e-12: the largest
-    difference relative to the largest entry."""
+    to rtol 1e-6) against the float64 form's converged one (rtol 1e-12): the
+    largest difference relative to the largest entry.  Stopping both solves
+    at relres 1e-6 is what limits it (the float64 form at the same rtol is
+    off by about as much; on the 64^3 version of this field the oracle's own
+    gradient at rtol 1e-6 is off by 2.4e-4), so the mixed form must stay
+    within 1.5 times the float64 form's error at rtol 1e-6 (and below 5e-3)."""
     kap, g = grf256_gradient
-    plan = etc.etc_setup(dev(kap, torch.float32), 0, precision="mixed", rtol=1e-6, want_grad=True)
-    assert etc.etc_solve(plan)["status"] == "ok"
-    gm = etc.etc_grad(plan).cpu().numpy()
-    plan.close()
-    err = np.abs(gm - g).max() / np.abs(g).max()
-    print(f"grf256 mixed gradient: max |g_mixed - g_f64| / max |g_f64| = {err:.3e}", flush=True)
-    assert err <= 2e-4, err
+    errs = {}
+    for precision in ("fp64", "mixed"):
+        plan = etc.etc_setup(dev(kap, torch.float32), 0, precision=precision, rtol=1e-6, want_grad=True)
+        assert etc.etc_solve(plan)["status"] == "ok"
+        gx = etc.etc_grad(plan).cpu().numpy()
+        plan.close()
+        errs[precision] = np.abs(gx - g).max() / np.abs(g).max()
+    print(f"grf256 gradient at rtol 1e-6: max |g - g_conv| / max |g_conv| = {errs['fp64']:.3e} (fp64), "
+          f"{errs['mixed']:.3e} (mixed)", flush=True)
+    assert errs["mixed"] <= 1.5 * errs["fp64"] + 1e-5, errs
+    assert errs["mixed"] <= 5e-3, errs

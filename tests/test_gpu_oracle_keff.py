@@ -7,11 +7,17 @@ Per workload the golden file holds the oracle's alg:pcg stopped at rtol 1e-6
 iteration continued to relres 1e-10 (the solution of A p = b).  On the GPU,
 in the launch configuration the benchmark times:
 
-* float64 form at rtol 1e-6 against the oracle's trajectory: K within 1e-8
-  relative, pass count within one;
-* float64 form against the oracle's solution: K within 1e-6 relative;
-* mixed form (float32 storage) against the oracle's solution: K within 1e-5
-  relative.
+* float64 form at rtol 1e-6 against the oracle run to the same rtol with the
+  same reference parameters and start: pass count within one, K within
+  1e-6 relative (the float64 bar).  Over a few tens of passes the two agree
+  to about 1e-11; over 140 or more passes of a contrast-1e3 field, rounding
+  differences between the FFT-based transforms and the oracle's O(N^2)
+  definitions move the stopping iterate by up to a few 1e-7;
+* float64 and mixed forms at rtol 1e-6 against the oracle's solution of
+  A p = b: K within 1e-5 relative (the scope's target bar).  Stopping at
+  relres 1e-6 itself leaves up to a few 1e-6 in K: the oracle's own rtol-1e-6
+  iterate misses its solution by 3.8e-6 on the 128^3 spheroids (load y),
+  so 1e-6 against the solution is not a bar the method reaches at this rtol.
 
 Each test first checks that the regenerated conductivity has the SHA-256
 recorded with the golden values.
@@ -65,13 +71,17 @@ def test_keff_matches_oracle(name, rve_inputs):
           f"iters={traj['iters']} truth K={truth['keff']:.12g}", flush=True)
     assert f64["status"] == "ok"
     assert np.allclose(f64["kref"], rec["kref"], rtol=1e-12, atol=0.0)
+    print(f"golden {name}: fp64 rel diff vs oracle traj {abs(f64['keff'] - traj['keff']) / traj['keff']:.2e}, "
+          f"vs solution {abs(f64['keff'] - truth['keff']) / truth['keff']:.2e}", flush=True)
     assert abs(f64["iters"] - traj["iters"]) <= 1
-    assert abs(f64["keff"] - traj["keff"]) <= 1e-8 * traj["keff"]
-    assert abs(f64["keff"] - truth["keff"]) <= 1e-6 * truth["keff"]
+    assert abs(f64["keff"] - traj["keff"]) <= 1e-6 * traj["keff"]
+    assert abs(f64["keff"] - truth["keff"]) <= 1e-5 * truth["keff"]
     mixed = run(kap, axis, "mixed")
     print(f"golden {name}: mixed K={mixed['keff']:.12g} iters={mixed['iters']} "
-          f"rel err vs truth {abs(mixed['keff'] - truth['keff']) / truth['keff']:.2e}", flush=True)
+          f"rel diff vs oracle traj {abs(mixed['keff'] - traj['keff']) / traj['keff']:.2e}, "
+          f"vs solution {abs(mixed['keff'] - truth['keff']) / truth['keff']:.2e}", flush=True)
     assert mixed["status"] == "ok"
+    assert abs(mixed["keff"] - traj["keff"]) <= 1e-5 * traj["keff"]
     assert abs(mixed["keff"] - truth["keff"]) <= 1e-5 * truth["keff"]
 
 
@@ -89,15 +99,18 @@ def test_spheres32_to_rtol_1e10_matches_oracle_solution(rve_inputs):
 def test_mixed_size_ensemble_matches_oracle(precision, tol, rve_inputs):
     """The ensemble RVEs of every edge (48 ... 160, float32 log-normal
     fields) solved together as one ensemble call: each K within the form's
-    bar of the oracle's solution."""
+    bar (1e-6 float64, 1e-5 mixed) of the oracle's rtol-1e-6 run, and within
+    1e-5 of the oracle's solution."""
     names = sorted((n for n in GOLD if n.startswith("ensemble")), key=lambda n: GOLD[n]["shape"][0])
     if not names:
         pytest.skip("no ensemble goldens")
     kaps = [torch.as_tensor(regenerate(n, rve_inputs), device="cuda:0") for n in names]
     out = etc.solve_ensemble(kaps, 0, precision=precision, rtol=1e-6)
     for i, n in enumerate(names):
-        truth = GOLD[n]["truth"]["keff"]
+        traj, truth = GOLD[n]["traj"]["keff"], GOLD[n]["truth"]["keff"]
         print(f"ensemble {precision} {n}: K={out['keff'][i]:.12g} iters={out['iters'][i]} "
-              f"rel {abs(out['keff'][i] - truth) / truth:.2e}", flush=True)
+              f"rel vs traj {abs(out['keff'][i] - traj) / traj:.2e} vs solution {abs(out['keff'][i] - truth) / truth:.2e}",
+              flush=True)
         assert out["status"][i] == "ok"
-        assert abs(out["keff"][i] - truth) <= tol * truth, n
+        assert abs(out["keff"][i] - traj) <= tol * traj, n
+        assert abs(out["keff"][i] - truth) <= 1e-5 * truth, n
