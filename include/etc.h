@@ -250,6 +250,33 @@ etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream)
 
 void etc_destroy(etc_plan* plan);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): etc_setup,
+ * etc_solve, etc_keff and (if p is non-NULL) etc_get_solution in one call,
+ * for one isotropic RVE, with every device buffer of the plan carved from a
+ * static device array of ETC_STATIC_SCRATCH_BYTES bytes that the library
+ * holds on each GPU it runs on until the process ends (48 MiB: room for
+ * 96^3 voxels in the float64 form, about 104^3 in the mixed form).  It calls
+ * no hipMalloc, hipHostMalloc, hipFree or other device or pinned-memory
+ * allocation; host bookkeeping uses the C++ heap.  The state mirror read
+ * every few passes lives in pageable host memory.
+ *   kappa, dt, n, bc, axis : as etc_setup (kappa borrowed for the call).
+ *   opt   : as etc_setup, or NULL; workspace must be NULL and autotune,
+ *           use_graph and want_grad 0 (else ETC_E_INVALID).
+ *   p     : device, user layout, float64, caller-owned, or NULL.
+ *   k_out : host, K_out of eq:effective formula dis; k_in nullable (host).
+ *   res   : as etc_solve, nullable.
+ * Returns ETC_E_UNSUPPORTED (and touches nothing) when etc_workspace_size for
+ * these arguments exceeds ETC_STATIC_SCRATCH_BYTES; otherwise what the calls
+ * it stands for return.  Every call on one GPU shares that GPU's array and
+ * overwrites it (setup rebuilds every buffer it reads, so the contents a
+ * previous call left do not matter): calls that overlap on one GPU, from
+ * several threads or streams, race and must be serialised by the caller.
+ * Synchronises the stream given in opt. */
+#define ETC_STATIC_SCRATCH_BYTES (48u << 20)
+etc_status etc_solve_static(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                            const etc_options* opt, double* p, double* k_out, double* k_in, etc_result* res);
+
 /* Message of the last failed call on the calling thread ("" if none). */
 const char* etc_last_error(void);
 

@@ -23,6 +23,7 @@ __all__ = [
     "etc_get_solution", "etc_residual_history", "etc_apply_A", "etc_apply_Minv", "etc_set_kernel_timer",
     "etc_kernel_time", "etc_copy_f64", "etc_destroy", "etc_last_error", "etc_version", "Plan", "solve",
     "STATUS", "etc_grad", "keff", "etc_setup_batch", "etc_batch_results", "etc_keff_batch", "solve_batch",
+    "etc_solve_static", "STATIC_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -119,11 +120,16 @@ _SYMBOLS = {
     "etc_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "etc_copy_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "etc_destroy": (None, [ctypes.c_void_p]),
+    "etc_solve_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC,
+                                        ctypes.c_int, ctypes.POINTER(_Options), ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_Result)]),
     "etc_last_error": (ctypes.c_char_p, []),
     "etc_version": (ctypes.c_char_p, []),
 }
 
 _lib = None
+STATIC_SCRATCH_BYTES = 48 << 20   # ETC_STATIC_SCRATCH_BYTES of include/etc.h
 
 
 def library_path() -> str:
@@ -301,6 +307,35 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
                                        int(axis), ctypes.byref(o), ctypes.byref(h)))
     del keep
     return Plan(h, ws, k0.shape, int(axis), precision, k0.device, stream)
+
+
+def etc_solve_static(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
+                     rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 20, poll_every: int = 8,
+                     kref: str = "mid", kref_user=None, L=None, precond: str = "dct", out=None) -> dict:
+    """Setup, solve and K_eff of one isotropic RVE in the library's static
+    scratch array (no device allocation, by the library or here): for
+    callers that cannot allocate.  ``out`` is an optional caller-owned
+    float64 tensor of kappa's shape that receives the solution."""
+    torch = _torch()
+    if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda" or kappa.dim() != 3:
+        raise ValueError("kappa must be a 3D torch tensor on a GPU device")
+    if kappa.dtype not in (torch.float64, torch.float32) or not kappa.is_contiguous():
+        raise ValueError("kappa must be a contiguous float64 or float32 tensor")
+    if out is not None and (out.dtype != torch.float64 or tuple(out.shape) != tuple(kappa.shape)
+                            or out.device != kappa.device or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 tensor of kappa's shape on kappa's device")
+    dtype = "float64" if kappa.dtype == torch.float64 else "float32"
+    stream = torch.cuda.current_stream(kappa.device)
+    o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
+                 False, precond, False, False)
+    k_out, k_in, res = ctypes.c_double(0.0), ctypes.c_double(0.0), _Result()
+    st = load_library().etc_solve_static(kappa.data_ptr(), _DTYPE[dtype], _dims(kappa.shape),
+                                         _BC(float(p_in), float(p_out)), int(axis), ctypes.byref(o),
+                                         None if out is None else out.data_ptr(), ctypes.byref(k_out),
+                                         ctypes.byref(k_in), ctypes.byref(res))
+    _check(st, allow_not_converged=True)
+    return {"keff": k_out.value, "k_in": k_in.value, "iters": res.iters, "status": STATUS[res.status],
+            "relres": res.relres, "kref": list(res.kref)}
 
 
 def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",

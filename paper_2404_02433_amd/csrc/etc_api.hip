@@ -111,7 +111,9 @@ struct etc_plan {
   double* hist;
   double* padj;       // adjoint state (want_grad), else nullptr
   void* dlt;          // mixed form: float32 solution increment since the last refinement
-  DevState* st_host;  // pinned, one per instance
+  DevState* st_host;  // pinned, one per instance (st_local for a scratch-array plan)
+  bool no_alloc;       // plan of etc_solve_static: scratch-array workspace, pageable state mirror
+  DevState st_local;
   DctPlan dpa, dpb;
   LaunchCfg lc;
   int nseg;                    // instances in the batch (1 for a single RVE)
@@ -1064,7 +1066,7 @@ etc_status etc_workspace_size_batch(const int64_t n[3], int nbatch, etc_dtype dt
 }  // extern "C"
 
 static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t n[3], int nseg, etc_bc bc, int axis,
-                             const etc_options* opt, etc_plan** out) {
+                             const etc_options* opt, etc_plan** out, bool no_alloc = false) {
   if (!out) return fail(ETC_E_INVALID, "plan is NULL");
   *out = nullptr;
   if (!pr) return fail(ETC_E_INVALID, "problem is NULL");
@@ -1143,7 +1145,11 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
     }
     P->ws_bytes = sz.total;
   }
-  if (hipHostMalloc((void**)&P->st_host, sizeof(DevState) * nseg, hipHostMallocDefault) != hipSuccess) {
+  P->no_alloc = no_alloc;
+  if (no_alloc) {
+    // one instance; its state is read back into pageable host memory
+    P->st_host = &P->st_local;
+  } else if (hipHostMalloc((void**)&P->st_host, sizeof(DevState) * nseg, hipHostMallocDefault) != hipSuccess) {
     if (P->own_ws) (void)hipFree(P->ws);
     delete P;
     return fail(ETC_E_NOMEM, "pinned host allocation failed");
@@ -1638,6 +1644,79 @@ etc_status etc_copy_f64(const double* src, double* dst, int64_t n, void* stream)
   return ETC_OK;
 }
 
+}  // extern "C"
+
+// Workspace of etc_solve_static: one array per GPU, held until the process
+// ends.  In host code the name `scratch` is only a stand-in for the symbol;
+// its device address comes from hipGetSymbolAddress, once per device, and
+// only that address is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[ETC_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+etc_status static_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ETC_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ETC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ETC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+etc_status etc_solve_static(const void* kappa, etc_dtype dt, const int64_t n[3], etc_bc bc, int axis,
+                            const etc_options* opt, double* p, double* k_out, double* k_in, etc_result* res) {
+  if (!k_out) return fail(ETC_E_INVALID, "k_out is NULL");
+  etc_options o;
+  if (opt) o = *opt;
+  else etc_options_default(&o);
+  if (o.workspace) return fail(ETC_E_INVALID, "etc_solve_static uses its own scratch array: workspace must be NULL");
+  if (o.autotune || o.use_graph || o.want_grad)
+    return fail(ETC_E_INVALID, "etc_solve_static: autotune, use_graph and want_grad must be 0");
+  size_t need = 0;
+  etc_status s = etc_workspace_size(n, dt, axis, &o, &need);
+  if (s) return s;
+  if (need > (size_t)ETC_STATIC_SCRATCH_BYTES)
+    return fail(ETC_E_UNSUPPORTED, "problem needs " + std::to_string(need) + " bytes of scratch; etc_solve_static holds " +
+                                       std::to_string((size_t)ETC_STATIC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  if ((s = static_scratch(&ws))) return s;
+  o.workspace = ws;
+  o.workspace_bytes = ETC_STATIC_SCRATCH_BYTES;
+  etc_problem pr;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.kappa[0] = kappa;
+  etc_plan* P = nullptr;
+  if ((s = setup_impl(&pr, dt, n, 1, bc, axis, &o, &P, true))) return s;
+  const etc_status st = etc_solve(P, nullptr, res);
+  if (st < 0) {
+    const std::string msg = g_err;
+    etc_destroy(P);
+    return fail(st, msg);
+  }
+  s = etc_keff(P, k_out, k_in, nullptr);
+  if (s == ETC_OK && p) s = etc_get_solution(P, p);
+  const std::string msg = g_err;
+  etc_destroy(P);
+  if (s) return fail(s, msg);
+  if (st == ETC_NOT_CONVERGED) g_err = "iteration cap reached";
+  return st;
+}
+
 void etc_destroy(etc_plan* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->stream);
@@ -1651,7 +1730,7 @@ void etc_destroy(etc_plan* P) {
   }
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   if (P->own_ws && P->ws) (void)hipFree(P->ws);
-  if (P->st_host) (void)hipHostFree(P->st_host);
+  if (P->st_host && !P->no_alloc) (void)hipHostFree(P->st_host);
   delete P;
 }
 

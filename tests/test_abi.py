@@ -105,3 +105,27 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
+
+
+def _static_call(shape, opts=None, k_out=True):
+    lib = etc.load_library()
+    o = etc._options(**(opts or {}))
+    ko, ki = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+    return lib.etc_solve_static(fake, 0, etc._dims(shape), etc._BC(1.0, 0.0), 0, ctypes.byref(o), None,
+                                ctypes.byref(ko) if k_out else None, ctypes.byref(ki), None)
+
+
+def test_static_entry_rejects_before_touching_the_device():
+    # beyond the static scratch array (128^3 float64 needs about 96 MiB)
+    assert etc.etc_workspace_size((128, 128, 128), "float64", 0) > etc.STATIC_SCRATCH_BYTES
+    assert _static_call((128, 128, 128)) == -6
+    assert "scratch" in etc.etc_last_error()
+    # a caller workspace, the autotuner, graphs or the adjoint are refused
+    assert _static_call((16, 16, 16), {"autotune": True}) == -1
+    assert _static_call((16, 16, 16), {"use_graph": True}) == -1
+    assert _static_call((16, 16, 16), {"want_grad": True}) == -1
+    assert _static_call((16, 16, 16), k_out=False) == -1
+    assert _static_call((1, 16, 16)) == -1
+    # the largest float64 cube the array holds
+    assert etc.etc_workspace_size((96, 96, 96), "float64", 0) <= etc.STATIC_SCRATCH_BYTES
