@@ -103,7 +103,6 @@ struct etc_plan {
   double* pout_face;
   double* p;
   void *r, *w, *q, *t;
-  double *lam_a, *lam_b;
   void *tw_a, *tw_b;
   double* partials;
   int max_partials;
@@ -124,7 +123,6 @@ struct etc_plan {
   bool any_done;  // some instance had converged at the last poll (batch plans)
   // host copies of the uploaded tables (kept until the plan ends, so that
   // their asynchronous uploads need no wait)
-  std::vector<double> lam_a_h, lam_b_h;
   std::vector<unsigned char> tw_a_h, tw_b_h;
   bool solved;
   int last_iters;              // max over instances
@@ -203,7 +201,7 @@ DctPlan make_dct_plan(int N) {
 }
 
 struct Sizes {
-  size_t off_kap_s, off_kap_hi, off_src, off_faces, off_p, off_r, off_w, off_q, off_t, off_lam_a, off_lam_b, off_tw_a, off_tw_b,
+  size_t off_kap_s, off_kap_hi, off_src, off_faces, off_p, off_r, off_w, off_q, off_t, off_tw_a, off_tw_b,
       off_kref, off_part, off_st, off_hist, off_padj, off_dlt, total;
   int max_partials;
 };
@@ -380,8 +378,6 @@ Sizes plan_sizes(const int64_t n[3], int axis, etc_dtype dt, const etc_options& 
   s.off_w = take(V * es);
   s.off_q = take(V * es);
   s.off_t = take(V * es);
-  s.off_lam_a = take(na * sizeof(double));
-  s.off_lam_b = take(nb * sizeof(double));
   s.off_tw_a = take((size_t)4 * na * 2 * es);
   s.off_tw_b = take((size_t)4 * nb * 2 * es);
   s.off_kref = take((size_t)5 * nseg * sizeof(double));
@@ -402,15 +398,6 @@ template <class T> void fill_twiddles(std::vector<cx<T>>& tw, int N) {
     const long double ang = -2.0L * pi * (long double)j / (4.0L * (long double)N);
     tw[j].re = (T)std::cos(ang);
     tw[j].im = (T)std::sin(ang);
-  }
-}
-
-void fill_lambda(std::vector<double>& lam, int N) {
-  lam.resize(N);
-  const long double pi = 3.141592653589793238462643383279502884L;
-  for (int k = 0; k < N; ++k) {
-    const long double sn = std::sin(pi * (long double)k / (2.0L * (long double)N));
-    lam[k] = (double)(4.0L * sn * sn);  // = 2 (1 - cos(k pi / N))
   }
 }
 
@@ -588,8 +575,9 @@ template <class S> struct Ops {
   static RefMedium ref(const etc_plan* P) {
     RefMedium rm;
     rm.kref = P->kref_d;
-    rm.lam_a = P->lam_a;
-    rm.lam_b = P->lam_b;
+    rm.step_a = 1.5707963267948966 / (double)P->g.na;
+    rm.step_b = 1.5707963267948966 / (double)P->g.nb;
+    rm.dot_scale = 4.0 / ((double)P->g.na * (double)P->g.nb);
     return rm;
   }
 
@@ -1173,8 +1161,6 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
   P->w = b + sz.off_w;
   P->q = b + sz.off_q;
   P->t = b + sz.off_t;
-  P->lam_a = (double*)(b + sz.off_lam_a);
-  P->lam_b = (double*)(b + sz.off_lam_b);
   P->tw_a = b + sz.off_tw_a;
   P->tw_b = b + sz.off_tw_b;
   P->kref_d = (double*)(b + sz.off_kref);
@@ -1214,11 +1200,9 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
         hipStreamSynchronize(P->stream) != hipSuccess)
       return bail(fail(ETC_E_HIP, "copying the Dirichlet face data failed"));
   }
-  // tables (independent of kappa): built on the host while the device makes
+  // DCT twiddle tables (independent of kappa): built on the host while the device makes
   // the canonical copy of the first instance, uploaded behind it
   auto upload_tables = [&]() -> etc_status {
-    fill_lambda(P->lam_a_h, na);
-    fill_lambda(P->lam_b_h, nb);
     if (P->prec == ETC_MIXED) {
       std::vector<cx<float>> a, c;
       fill_twiddles(a, na);
@@ -1232,11 +1216,7 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
       P->tw_a_h.assign((unsigned char*)a.data(), (unsigned char*)(a.data() + a.size()));
       P->tw_b_h.assign((unsigned char*)c.data(), (unsigned char*)(c.data() + c.size()));
     }
-    if (hipMemcpyAsync(P->lam_a, P->lam_a_h.data(), na * sizeof(double), hipMemcpyHostToDevice, P->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(P->lam_b, P->lam_b_h.data(), nb * sizeof(double), hipMemcpyHostToDevice, P->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(P->tw_a, P->tw_a_h.data(), P->tw_a_h.size(), hipMemcpyHostToDevice, P->stream) !=
+    if (hipMemcpyAsync(P->tw_a, P->tw_a_h.data(), P->tw_a_h.size(), hipMemcpyHostToDevice, P->stream) !=
             hipSuccess ||
         hipMemcpyAsync(P->tw_b, P->tw_b_h.data(), P->tw_b_h.size(), hipMemcpyHostToDevice, P->stream) !=
             hipSuccess)

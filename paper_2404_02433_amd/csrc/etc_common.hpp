@@ -16,13 +16,14 @@ struct Geo {
   double p_in, p_out;
 };
 
-// Reference-medium parameters (per instance: kL ka kb kin kout) and per-mode
-// eigenvalue tables of the preconditioner (tridiagonal shift
-// lambda_a * ka + lambda_b * kb).
+// Reference-medium parameters (per instance: kL ka kb kin kout) and what the
+// tridiagonal kernel needs to form a mode's shift lambda_a ka + lambda_b kb
+// (lambda(k) = 4 sin^2(k step), step = pi / (2 N) per transverse axis) and to
+// scale its r . z partials.  Kernel arguments, so they sit in scalar registers.
 struct RefMedium {
-  const double* kref;   // 5 per instance
-  const double* lam_a;  // length na, 4 sin^2(pi a' / (2 na))
-  const double* lam_b;  // length nb
+  const double* kref;      // 5 per instance
+  double step_a, step_b;   // pi / (2 na), pi / (2 nb)
+  double dot_scale;        // 4 / (na nb), Parseval weight of the transformed dot product
 };
 
 // Solver state kept in device memory so the host never waits per dot product.

@@ -1347,6 +1347,31 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
 
 // =================================================================== Thomas
 
+// lambda(k) = 2 (1 - cos(k pi / N)) = 4 sin^2(k pi / (2 N)), the eigenvalues
+// of the 1D Neumann matrix (Section "Preconditioner system solver"), for
+// 0 <= k < N, with step = pi / (2 N).  The argument lies in [0, pi/2), where
+// the Taylor series of sin through x^23 is exact to double rounding (the
+// next term is below 1e-19 of the sum); Horner in x^2.  No memory access,
+// so the tridiagonal kernel forms a mode's shift without a load.
+__device__ __forceinline__ double neumann_lambda(int k, double step) {
+  const double x = (double)k * step;
+  const double x2 = x * x;
+  double sp = 1.0 / 25852016738884976640000.0;          // 1/23!
+  sp = fma(sp, -x2, 1.0 / 51090942171709440000.0);      // 1/21!
+  sp = fma(sp, -x2, 1.0 / 121645100408832000.0);        // 1/19!
+  sp = fma(sp, -x2, 1.0 / 355687428096000.0);           // 1/17!
+  sp = fma(sp, -x2, 1.0 / 1307674368000.0);             // 1/15!
+  sp = fma(sp, -x2, 1.0 / 6227020800.0);                // 1/13!
+  sp = fma(sp, -x2, 1.0 / 39916800.0);                  // 1/11!
+  sp = fma(sp, -x2, 1.0 / 362880.0);                    // 1/9!
+  sp = fma(sp, -x2, 1.0 / 5040.0);                      // 1/7!
+  sp = fma(sp, -x2, 1.0 / 120.0);                       // 1/5!
+  sp = fma(sp, -x2, 1.0 / 6.0);                         // 1/3!
+  sp = fma(sp, -x2, 1.0);
+  const double sn = x * sp;
+  return 4.0 * sn * sn;
+}
+
 // Solve T_{a',b'} z = t along k for every transverse mode (a', b'), in place,
 // with double arithmetic.  T = s I + kL tridiag(-1, 2, -1), first and last
 // diagonal entries s + kL + 2 kin and s + kL + 2 kout, s = lam_a ka + lam_b kb.
@@ -1368,13 +1393,20 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
 // (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r;
 // per block, t . z = t^T M^{-1} t + (coupling) * (ends of M^{-1} t).
 //
+// The mode's shift s comes from eigenvalues computed in registers
+// (neumann_lambda), not from a table in memory.
+//
 // Blocks are persistent: block x of instance z handles tiles x, x + gridDim.x,
-// ... (a tile is TB modes b' of one mode a').  PF: the block loads the next
-// tile's rows into registers before it works on the current one, so HBM
-// traffic overlaps the elimination (float32 rows; float64 rows would cost
-// the registers of a second block per CU, which hides latency better).
-// EXACT: nL = P * MAXM (every partition has MAXM rows), which removes the
-// ragged-length guards.
+// ... (a tile is TB modes b' of one mode a'; consecutive blocks take adjacent
+// tiles, so the rows in flight at one time cover long runs of each plane).
+// PF: the block loads the next tile's rows into registers before it works on
+// the current one, so HBM traffic overlaps the elimination (float32 rows;
+// float64 rows would cost the registers of a second block per CU, which hides
+// latency better).  Loads and stores share one in-order counter per wave, so
+// the prefetched rows are taken (waited for) before the current tile's
+// stores are issued, and the shift needs no load: a wait placed after the
+// stores would also wait for them to drain.  EXACT: nL = P * MAXM (every
+// partition has MAXM rows), which removes the ragged-length guards.
 template <class S, int TB, int P, int MAXM, bool EXACT, bool PF = ((EXACT && sizeof(S) == 4) || MAXM <= 8)>
 __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
@@ -1397,7 +1429,7 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
   const bool right = pok && (p < Peff - 1);  // partition ends in a separator row
   const int endp = min(start + m, nL);
   const int lenp = pok ? (endp - start - (right ? 1 : 0)) : 0;
-  const double kL = kr[0];
+  const double kL = kr[0], ka = kr[1], kb = kr[2];
   const double aoff = -kL;
   const double a2 = kL * kL;
   const double Dint0 = 2.0 * kL;
@@ -1424,24 +1456,30 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
   // tiles of one round are renumbered so that each XCD holds a contiguous
   // range (adjacent tiles share 128-byte lines when TB * sizeof(S) < 128)
   S cur[MAXM], cur_s = S(0);
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (PF && tile < ntiles) load(tile, cur, cur_s);
+  int tile = blockIdx.x;
+  if (PF && tile < ntiles) {
+    load(tile, cur, cur_s);
+    // wait for the first tile here, outside the loop, so that the loop head
+    // never waits (a wait there would also cover the previous tile's stores)
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j) asm volatile("" ::"v"(cur[j]));
+    asm volatile("" ::"v"(cur_s));
+  }
   for (; tile < ntiles; tile += gridDim.x) {
     const int bm = (tile % ntx) * TB + l, am = tile / ntx;
     const bool line_ok = bm < g.nb;
     const bool active = line_ok && pok;
     const bool has_right = active && right;
     const int len = active ? lenp : 0;
-    const double sft = line_ok ? (rm.lam_a[am] * kr[1] + rm.lam_b[bm] * kr[2]) : 0.0;
+    // the mode's shift from the eigenvalues computed in registers: a load here
+    // would wait behind the previous tile's stores in the in-order counter
+    const double sft = line_ok ? (neumann_lambda(am, rm.step_a) * ka + neumann_lambda(bm, rm.step_b) * kb) : 0.0;
     const double Dint = sft + Dint0;
     S nxt[PF ? MAXM : 1], nxt_s = S(0);
     if constexpr (PF) {
-      // One counter tracks every vector load in order, so any wait issued
-      // after the prefetch (for the shift above or this tile's rows) would
-      // also wait for the whole prefetch: take both into registers first.
-#pragma unroll
-      for (int j = 0; j < MAXM; ++j) asm volatile("" ::"v"(cur[j]));
-      asm volatile("" ::"v"(cur_s), "v"(Dint));
+      // this tile's rows arrived before the loop head (first tile) or were
+      // taken before the previous tile's stores; the shift is in registers
+      asm volatile("" ::"v"(Dint));
       const int tn = tile + gridDim.x;
       if (tn < ntiles) load(tn, nxt, nxt_s);
     } else {
@@ -1533,10 +1571,10 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
     __syncthreads();
     if (sep) sh[5][q][l] = rq / Bq;  // separator value x_q
     __syncthreads();
-    double acc = 0.0;
+    double acc = 0.0, zr = 0.0;
     if (active) {
       const double zl = (p > 0) ? sh[5][p - 1][l] : 0.0;
-      const double zr = has_right ? sh[5][p][l] : 0.0;
+      zr = has_right ? sh[5][p][l] : 0.0;
       const double c1 = -aoff * zl, cm = -aoff * zr;
       // z = M^{-1} (t + c1 e_1 + cm e_len): forward elimination with the
       // couplings at both ends, then back substitution, both with the stored
@@ -1563,22 +1601,32 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
             cur[j] = z;
           } else {
             z = (j == lastj) ? dv[j] : (dv[j] - aoff * invu[j] * z);
-            dv[j] = z;
+            cur[j] = (S)z;  // this tile's rows are dead after the forward pass
           }
         }
       }
+      const double wa = (am == 0) ? 0.5 : 1.0, wb = (bm == 0) ? 0.5 : 1.0;
+      acc = wa * wb * (quad + c1 * y_first + cm * y_last + (has_right ? ts * zr : 0.0));
+    }
+    if constexpr (PF) {
+      // Loads and stores share one in-order counter per wave: take the
+      // prefetched tile now, on every path, so that no later wait for it
+      // also waits for this tile's stores.
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) asm volatile("" ::"v"(nxt[j]) : "memory");
+      asm volatile("" ::"v"(nxt_s) : "memory");
+    }
+    if (active) {
       S* dst = t + (int64_t)start * plane + (int64_t)am * g.nb + bm;
 #pragma unroll
       for (int j = 0; j < MAXM; ++j)
         if ((EXACT && (j < MAXM - 1 || !has_right)) || (!EXACT && j < len))
-          dst[(int64_t)j * plane] = (sizeof(S) == 8) ? cur[j] : (S)dv[j];
+          dst[(int64_t)j * plane] = cur[j];
       if (has_right) dst[(int64_t)(endp - 1 - start) * plane] = (S)zr;
-      const double wa = (am == 0) ? 0.5 : 1.0, wb = (bm == 0) ? 0.5 : 1.0;
-      acc = wa * wb * (quad + c1 * y_first + cm * y_last + (has_right ? ts * zr : 0.0));
     }
     if (partials) {
       const double sum = block_sum(acc, red);
-      if (tid == 0) partials[tile] = sum * (4.0 / ((double)g.na * (double)g.nb));
+      if (tid == 0) partials[tile] = sum * rm.dot_scale;
     }
     __syncthreads();  // the next tile rewrites sh
     if constexpr (PF) {
@@ -1588,6 +1636,7 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
     }
   }
 }
+
 
 // ================================================================ finalize
 enum FinOp { FIN_BNORM = 0, FIN_RHO0, FIN_ALPHA, FIN_RR, FIN_REFINE, FIN_BETA, FIN_RR0, FIN_ACC0, FIN_ACC1, FIN_ACC2, FIN_ACC3 };
