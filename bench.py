@@ -13,8 +13,12 @@ spheres, load along x, Dirichlet 1 / 0.
 Extra fields: the float64 form's time, both K_eff values and iteration
 counts, the achieved HBM rate of the whole solve (algorithmic bytes / time),
 the roofline record of the dominant kernel (HIP-event timing around its
-launches inside the timed region) and the CPU oracle's time on a bounded
-sample of the same workload.
+launches inside the timed region), a per-kernel census of all six hot
+kernels per form (one extra solve per kernel after the timed region, HIP
+events around that kernel's launches), the literal 2000-sphere 512^3
+workload timed the same way, and the CPU oracle's time on a bounded sample
+of the same workload (with the CPU model, the BLAS threads the oracle uses
+and the recorded time of one whole oracle solve).
 """
 
 from __future__ import annotations
@@ -128,11 +132,60 @@ def cpu_baseline(kap_np, iters_full: int, slab: int = 128, sample_iters: int = 2
     per_pass = t_pcg / (res.iters + 1)   # initial preconditioner pass + sample passes
     scale = nL / sub.shape[0]
     est = scale * (t_setup + per_pass * (iters_full + 1))
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
-    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sub.shape[0]} of {nL} load planes of the same RVE: oracle setup + initial pass + "
-                      f"{res.iters} PCG passes timed ({t_setup + t_pcg:.1f} s), scaled by {scale:g} (plane count) "
-                      f"and to {iters_full} passes"}
+    blas = blas_threads()
+    out = {"value": est, "unit": "s", "cores": blas, "kind": "oracle",
+           "sample": f"first {sub.shape[0]} of {nL} load planes of the same RVE: oracle setup + initial pass + "
+                     f"{res.iters} PCG passes timed ({t_setup + t_pcg:.1f} s), scaled by {scale:g} (plane count) "
+                     f"and to {iters_full} passes",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "threads_note": f"the oracle's DCTs (matrix products) use {blas} BLAS threads; its stencil, "
+                           "tridiagonal sweeps and vector updates run on one thread"}
+    full = measured_full_oracle_solve()
+    if full:
+        out["measured_full_solve"] = full
+    return out
+
+
+def blas_threads() -> int:
+    """Threads of NumPy's BLAS (the only multi-threaded part of the oracle)."""
+    try:
+        import numpy as np
+        from threadpoolctl import threadpool_info
+
+        np.ones((2, 2)) @ np.ones((2, 2))
+        n = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(n[0])
+    except Exception:
+        pass
+    return int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", 1)))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measured_full_oracle_solve():
+    """The whole 512^3 oracle solve (alg:pcg to rtol 1e-6, 55 passes) as
+    recorded with the stored oracle K_eff values (a separate CPU run, not this
+    host), for context beside the sampled estimate."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_keff.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get("spheres512")
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    return {"seconds": rec["traj"]["seconds"], "passes": rec["traj"]["iters"],
+            "blas_threads": rec.get("blas_threads"), "where": "build container CPU (recorded in tests/golden/oracle_keff.json)"}
 
 
 def ensemble_bench(torch, etc, rvegen, args):
@@ -176,6 +229,23 @@ def ensemble_bench(torch, etc, rvegen, args):
     print(json.dumps(line), flush=True)
 
 
+def leg_2000(torch, etc, rvegen, args, forms):
+    """The literal 2000-sphere 512^3 workload (r = 10, vf ~0.062), timed like
+    the headline workload (same steps and warm-up, per form)."""
+    print("bench: generating spheres512_2000", file=sys.stderr, flush=True)
+    kap_np, info = rvegen.make_config("spheres512_2000")
+    kap = torch.as_tensor(kap_np, device="cuda:0")
+    out = {"workload": f"512^3 two-phase RVE, {info['spheres']} non-overlapping spheres r=10 (vf={info['vf']:.4f}), "
+                       f"kappa 1/100, load x, rtol {args.rtol:g}"}
+    for form in forms:
+        print(f"bench: timing {form} (2000 spheres)", file=sys.stderr, flush=True)
+        dt, outs = time_form(torch, etc, kap, form, args.rtol, args.steps, args.warmup, 0, args.autotune)
+        o = outs[-1]
+        out[form] = {"time_s": dt, "iters": o["iters"], "keff": o["keff"], "relres": o["relres"], "status": o["status"]}
+    del kap
+    return out
+
+
 def copy_rate(torch, etc, mib: int = 1024, reps: int = 10) -> float:
     """HBM rate of a plain streaming copy (read + write bytes / time), the
     practical ceiling that the hot kernels are also compared with."""
@@ -208,6 +278,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--kernel", type=int, default=6, help="hot kernel timed with HIP events (1-6)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-census", action="store_true", help="skip the per-kernel timing solves")
+    ap.add_argument("--no-2000", action="store_true", help="skip the 2000-sphere workload leg")
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run the plain copy kernel on MIB MiB (5 launches) and exit; the byte counters "
@@ -262,6 +334,25 @@ def main():
                      "kernel_avg_ms": kms}
         print(f"bench: {form} {dt:.4f} s/solve iters={o['iters']} keff={o['keff']:.8f}", file=sys.stderr, flush=True)
 
+    # per-kernel census (outside the timed region): one solve per hot kernel
+    # with HIP events around every launch of that kernel
+    copy_gbs = copy_rate(torch, etc)
+    if not args.no_census:
+        for form in forms:
+            print(f"bench: kernel census {form}", file=sys.stderr, flush=True)
+            es = 4 if form == "mixed" else 8
+            census = {}
+            for kid in range(1, 7):
+                o = run_solve(etc, kap, form, args.rtol, kid, args.autotune)
+                ms = o["kernel_ms"] / max(1, o["kernel_launches"])
+                bpl = bytes_per_voxel(kid, es) * V
+                gbs = bpl / (ms * 1e-3) / 1e9
+                census[KERNEL_NAMES[kid]] = {"avg_launch_ms": ms, "launches": o["kernel_launches"],
+                                             "algorithmic_bytes_per_launch": bpl, "achieved_gbs": gbs,
+                                             "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs,
+                                             "traffic": measured_traffic(kid, "spheres512", form)}
+            res[form]["kernels"] = census
+
     head = "mixed" if "mixed" in res else forms[0]
     es = 4 if head == "mixed" else 8
     kid = args.kernel
@@ -269,7 +360,6 @@ def main():
     kms = res[head]["kernel_avg_ms"]
     achieved = bpl / (kms * 1e-3) / 1e9 if kms > 0 else None
     traffic = measured_traffic(kid, "spheres512", head)
-    copy_gbs = copy_rate(torch, etc)
     roof = {"bound": "hbm", "kernel": KERNEL_NAMES[kid], "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "algorithmic_bytes_per_launch": bpl, "avg_launch_ms": kms,
@@ -296,6 +386,8 @@ def main():
         "hbm_gbs": res[head]["hbm_gbs"],
         "roofline": roof,
     }
+    if not args.no_2000 and args.n == 512:
+        line["spheres512_2000"] = leg_2000(torch, etc, rvegen, args, forms)
     if not args.no_cpu:
         print("bench: cpu oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(kap_np, res[head]["iters"])

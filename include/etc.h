@@ -138,9 +138,13 @@ etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const 
  * "Performance tests of different implementations"): validates the arguments,
  * copies `kappa` (device, user layout, dtype `dt`) into the canonical layout,
  * checks every conductivity is finite and > 0, computes the family extrema and
- * the reference parameters, and builds the DCT twiddle and eigenvalue tables.
+ * the reference parameters, and builds the DCT twiddle tables.
  *   kappa : borrowed for the duration of the call only.
- *   n     : user dims; each >= 1, n[axis] >= 2, product < 2^31 per plane.
+ *   n     : user dims; each >= 1 and <= 2^20, n[axis] >= 2.  Beyond the
+ *           kernels' limits ETC_E_UNSUPPORTED: load axis n[axis] <= 2048 (the
+ *           tridiagonal kernel holds a line as 32 partitions of at most 64
+ *           rows), first transverse axis <= 65535, transverse plane < 2^31
+ *           voxels.
  *   bc    : p_in != p_out (eq:effective formula needs a drop).
  *   opt   : may be NULL (defaults).  If opt->workspace is NULL the plan
  *           allocates its device memory with hipMalloc and frees it in

@@ -32,6 +32,7 @@ __all__ = [
     "series_laminate",
     "parallel_laminate",
     "random_two_phase",
+    "channels",
     "CONFIGS",
     "make_config",
 ]
@@ -228,6 +229,24 @@ def random_two_phase(shape, seed: int, kappa=(1.0, 10.0), p: float = 0.3) -> np.
     """Independent Bernoulli(p) voxels taking kappa[1], else kappa[0]."""
     rng = np.random.default_rng(seed)
     return np.where(rng.random(shape) < p, float(kappa[1]), float(kappa[0]))
+
+
+def channels(n: int, cells: int, psi: float, dtype=np.float64):
+    """Periodic channel cells with orthotropic conductivity (Section "Other
+    experiments", fig:channels-cell): the unit cell holds three orthogonal
+    square bars, each spanning the cell along one axis with its cross-section
+    (3/8, 5/8)^2 in the other two; inside a bar K = diag(2^psi, 5^psi, 10^psi),
+    elsewhere diag(0.01, 0.1, 1).  The RVE (0,1)^3 repeats the cell `cells`
+    times per axis and is sampled at the n^3 voxel centres.  Returns the
+    conductivity along user axes 0, 1, 2 (x, y, z)."""
+    c = np.modf((np.arange(n) + 0.5) / n * cells)[0]        # fractional cell coordinate per index
+    mid = (c > 3 / 8) & (c < 5 / 8)
+    X, Y, Z = mid[:, None, None], mid[None, :, None], mid[None, None, :]
+    bar = (Y & Z) | (X & Z) | (X & Y)
+    out = []
+    for inside, outside in zip((2.0 ** psi, 5.0 ** psi, 10.0 ** psi), (0.01, 0.1, 1.0)):
+        out.append(np.where(bar, inside, outside).astype(dtype))
+    return tuple(out)
 
 
 @dataclass
