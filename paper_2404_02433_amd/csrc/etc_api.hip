@@ -127,11 +127,14 @@ struct etc_plan {
   bool solved;
   int last_iters;              // max over instances
   int last_status;             // worst over instances
-  // captured passes (use_graph): one graph per (solution buffer, Dirichlet pair)
+  // captured passes (use_graph): one graph per (solution buffer, Dirichlet
+  // pair, whether an instance of the batch has converged: the column
+  // transforms launched differ)
   hipStream_t cstream;         // capture/replay stream owned by the plan (or nullptr)
   struct GraphEntry {
     double* p;
     double p_in, p_out;
+    bool any_done;
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
@@ -1317,13 +1320,13 @@ static etc_status graph_for(etc_plan* P, hipGraphExec_t* out, hipStream_t* ls) {
   }
   *ls = cs;
   for (auto& e : P->graphs)
-    if (e.p == P->p && e.p_in == P->g.p_in && e.p_out == P->g.p_out) {
+    if (e.p == P->p && e.p_in == P->g.p_in && e.p_out == P->g.p_out && e.any_done == P->any_done) {
       *out = e.exec;
       return ETC_OK;
     }
   const hipStream_t saved = P->stream;
   P->stream = cs;
-  etc_plan::GraphEntry e{P->p, P->g.p_in, P->g.p_out, nullptr, nullptr};
+  etc_plan::GraphEntry e{P->p, P->g.p_in, P->g.p_out, P->any_done, nullptr, nullptr};
   etc_status s = ETC_OK;
   hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (he == hipSuccess) {
@@ -1401,8 +1404,14 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
     if ((s = pull_state(P))) return s;
     bool all_done = true;
     for (int i = 0; i < P->nseg; ++i) all_done = all_done && P->st_host[i].done;
+    const bool was_done = P->any_done;
     for (int i = 0; i < P->nseg; ++i) P->any_done = P->any_done || P->st_host[i].done;
     if (all_done || enq > P->opt.max_iter) break;
+    if (exec && P->any_done != was_done) {
+      // an instance has converged: from here the passes gate the column
+      // transforms, which is another captured graph
+      if ((s = graph_for(P, &exec, &gstream))) return s;
+    }
     if (exec) {
       HIPCHK(hipGraphLaunch(exec, gstream));
     } else {

@@ -497,6 +497,26 @@ def test_graph_batch_and_side_stream():
     assert out["keff"] == ref["keff"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_batch_with_persistent_column_kernels(precision):
+    """Graph replay on a batch whose column length (64) has the persistent
+    column kernels and whose instances converge at different passes: the
+    plan keeps one captured graph per converged-instance state (persistent
+    column kernels until an instance converges, gated ones after), so the
+    replayed passes launch what the eager passes launch and give the same
+    pass counts and K_eff bit for bit."""
+    shape = (16, 64, 64)
+    kaps = np.stack([np.exp(s * np.random.default_rng(300 + i).standard_normal(shape))
+                     for i, s in enumerate([0.1, 0.8, 1.5])])
+    rtol = 1e-10 if precision == "fp64" else 1e-6
+    eager = etc.solve_batch(dev(kaps), 0, precision=precision, rtol=rtol)
+    graph = etc.solve_batch(dev(kaps), 0, precision=precision, rtol=rtol, use_graph=True)
+    assert len(set(eager["iters"])) > 1
+    assert graph["status"] == eager["status"]
+    assert graph["iters"] == eager["iters"]
+    assert graph["keff"] == eager["keff"]
+
+
 # --------------------------------------------------------------- ensembles
 @pytest.mark.parametrize("concurrent", [True, False])
 def test_ensemble_of_mixed_sizes_matches_oracle(concurrent):
