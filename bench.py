@@ -16,7 +16,8 @@ the roofline record of the dominant kernel (HIP-event timing around its
 launches inside the timed region), a per-kernel census of all six hot
 kernels per form (one extra solve per kernel after the timed region, HIP
 events around that kernel's launches), the literal 2000-sphere 512^3
-workload timed the same way, and the CPU oracle's time on a bounded sample
+workload timed the same way, the mixed-size GRF ensemble (64 RVEs in one
+ensemble plan: RVEs/s, passes/s, HBM rate), and the CPU oracle's time on a bounded sample
 of the same workload (with the CPU model, the BLAS threads the oracle uses
 and the recorded time of one whole oracle solve).
 """
@@ -188,18 +189,44 @@ def measured_full_oracle_solve():
             "blas_threads": rec.get("blas_threads"), "where": "build container CPU (recorded in tests/golden/oracle_keff.json)"}
 
 
-def ensemble_bench(torch, etc, rvegen, args):
-    """Ensemble of 64 log-normal GRF RVEs of mixed edges {48, 64, 96, 128, 160}
-    (per-RVE variance U[0.5, 2], correlation length U[4, 16], contrast <= 1e3,
-    float32 input), mixed form, load x, rtol 1e-6.  A step solves every RVE
-    (same-size RVEs share a batch plan) and reads back every K_eff."""
-    print("bench: generating the GRF ensemble", file=sys.stderr, flush=True)
-    kaps_np, specs = rvegen.grf_ensemble(args.ensemble)
+def _grf_one(spec):
+    import numpy as np
+    import rvegen
+
+    return rvegen.grf_lognormal(spec["n"], spec["sigma2"], spec["ell"], spec["seed"], 1e3, np.float32)
+
+
+def grf_ensemble_parallel(rvegen, count, workers=8):
+    """The seeded GRF ensemble, each RVE generated in a worker process (the
+    same arrays as rvegen.grf_ensemble, which builds them one after another).
+    Called before anything touches the GPU, so the workers are forked from a
+    process without device state."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    print(f"bench: generating the GRF ensemble ({count} RVEs)", file=sys.stderr, flush=True)
+    specs = rvegen.grf_ensemble_specs(count)
+    workers = max(1, min(workers, (os.cpu_count() or 1) // 2))
+    if workers == 1:
+        return [_grf_one(sp) for sp in specs], specs
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        kaps = list(ex.map(_grf_one, specs))
+    return kaps, specs
+
+
+def ensemble_record(torch, etc, rvegen, args, ens, form, mode="launch", graph=False):
+    """Ensemble of `count` log-normal GRF RVEs of mixed edges {48, 64, 96, 128,
+    160} (per-RVE variance U[0.5, 2], correlation length U[4, 16], contrast
+    <= 1e3, float32 input), load x, rtol 1e-6.  A step solves every RVE and
+    reads back every K_eff; mode "launch" is one ensemble plan (every kernel
+    of a pass one launch for all RVEs), "plans" the per-shape batch plans on
+    concurrent streams."""
+    kaps_np, specs = ens
     kaps = [torch.as_tensor(k, device="cuda:0") for k in kaps_np]
     V = sum(k.size for k in kaps_np)
-    form = args.forms.split(",")[0]
-    kw = dict(precision=form, rtol=args.rtol, use_graph=args.graph, concurrent=not args.serial,
-              max_batch_voxels=args.batch_voxels)
+    kw = dict(precision=form, rtol=args.rtol, use_graph=graph, mode=mode)
+    if mode == "plans":
+        kw.update(concurrent=not args.serial, max_batch_voxels=args.batch_voxels)
+    print(f"bench: timing the ensemble ({form}, {mode})", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         etc.solve_ensemble(kaps, 0, **kw)
     torch.cuda.synchronize()
@@ -211,20 +238,33 @@ def ensemble_bench(torch, etc, rvegen, args):
     es = 4 if form == "mixed" else 8
     it_bytes = sum(iteration_bytes_per_voxel(es, form == "mixed", 20) * k.size * it
                    for k, it in zip(kaps_np, out["iters"]))
+    gbs = it_bytes / dt / 1e9
+    del kaps
+    return {
+        "workload": f"grf_ensemble: {len(kaps_np)} log-normal GRF RVEs, edges 48/64/96/128/160, "
+                    f"{V / 1e6:.1f} M voxels in total, load x, rtol {args.rtol:g}",
+        "form": form, "mode": mode, "graph": bool(graph),
+        "rves_per_s": len(kaps_np) / dt, "s_per_ensemble": dt,
+        "passes_per_s": sum(out["iters"]) / dt, "iters_min_max": [min(out["iters"]), max(out["iters"])],
+        "all_ok": all(st == "ok" for st in out["status"]), "plans": out["plans"],
+        "hbm_gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+    }
+
+
+def ensemble_bench(torch, etc, rvegen, args):
+    """Ensemble benchmark alone (RVEs/s as the metric)."""
+    form = args.forms.split(",")[0]
+    ens = grf_ensemble_parallel(rvegen, args.ensemble, args.gen_workers)
+    rec = ensemble_record(torch, etc, rvegen, args, ens, form, args.ensemble_mode, args.graph)
     line = {
         "metric": "RVE ensemble throughput (64 mixed-size GRF RVEs to rel.res 1e-6)",
-        "value": len(kaps) / dt, "unit": "RVEs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": rec["rves_per_s"], "unit": "RVEs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": rec["s_per_ensemble"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
         "dtype": "f32 storage / f64 dots+tridiagonal+refinement" if form == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"grf_ensemble: {len(kaps)} log-normal GRF RVEs, edges 48/64/96/128/160, "
-                               f"{V / 1e6:.1f} M voxels in total, load x, rtol {args.rtol:g}", "form": form,
-                   "graph": bool(args.graph), "concurrent_plans": not args.serial,
-                   "max_batch_voxels": args.batch_voxels},
-        "plans": out["plans"],
-        "iters_min_max": [min(out["iters"]), max(out["iters"])],
-        "all_ok": all(s == "ok" for s in out["status"]),
-        "hbm_gbs": it_bytes / dt / 1e9,
+        "data": "synthetic", "config": {"workload": rec["workload"], "form": form, "mode": rec["mode"],
+                                        "graph": rec["graph"]},
+        "ensemble": rec,
     }
     print(json.dumps(line), flush=True)
 
@@ -288,6 +328,11 @@ def main():
                     help="time the mixed-size GRF ensemble of COUNT RVEs instead (RVEs/s)")
     ap.add_argument("--graph", action="store_true", help="replay the PCG passes from captured HIP graphs")
     ap.add_argument("--serial", action="store_true", help="ensemble: run the batch plans one after another")
+    ap.add_argument("--ensemble-mode", default="launch", choices=["launch", "plans"],
+                    help="ensemble: one plan with multi-group launches, or per-shape batch plans")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble record of the default run")
+    ap.add_argument("--gen-workers", type=int, default=8,
+                    help="processes generating the ensemble's fields (1: in this process, e.g. under a profiler)")
     ap.add_argument("--autotune", action="store_true",
                     help="plans tune their launch shapes at setup (the warm-up solve pays for the tuning)")
     ap.add_argument("--batch-voxels", type=int, default=1 << 25, help="ensemble: voxel cap of one batch plan")
@@ -301,6 +346,10 @@ def main():
 
     import paper_2404_02433_amd as etc
     import rvegen
+
+    # the ensemble's arrays are generated first, before any device work
+    ens = grf_ensemble_parallel(rvegen, 64, args.gen_workers) if (not args.no_ensemble and not args.ensemble
+                                                and not args.copy_calib) else None
 
     if args.copy_calib:
         n = args.copy_calib * (1 << 20) // 8
@@ -388,6 +437,9 @@ def main():
     }
     if not args.no_2000 and args.n == 512:
         line["spheres512_2000"] = leg_2000(torch, etc, rvegen, args, forms)
+    if ens is not None:
+        line["ensemble"] = ensemble_record(torch, etc, rvegen, args, ens, "mixed")
+        del ens
     if not args.no_cpu:
         print("bench: cpu oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(kap_np, res[head]["iters"])

@@ -179,6 +179,31 @@ etc_status etc_setup_batch(const void* kappa, etc_dtype dt, const int64_t n[3], 
 etc_status etc_workspace_size_batch(const int64_t n[3], int nbatch, etc_dtype dt, int axis, const etc_options* opt,
                                     size_t* bytes);
 
+/* A mixed-size ensemble: `count` independent isotropic RVEs, RVE i a
+ * C-contiguous device array kappa[i] (user layout, dtype dt) of dims
+ * dims[3i..3i+2], one load axis and one Dirichlet pair for all (Section
+ * "Remarks on implementations": the transforms and tridiagonal systems of
+ * many problems are batched).  RVEs of one shape form a group (at most 8
+ * distinct shapes; load axes up to 512 voxels); every kernel of a PCG pass is
+ * ONE launch for the whole ensemble, whose blocks pick their group and run
+ * the kernel variant that group's size has, and every RVE keeps its own
+ * reference medium, PCG scalars, exit test and convergence flag (converged
+ * RVEs are skipped by every later kernel).  With opt->use_graph the passes
+ * between host polls are replayed from one captured graph.
+ *   kappa : count device pointers, borrowed for the duration of the call.
+ *   opt   : as etc_setup; opt->workspace, when given, must hold
+ *           etc_workspace_size_ensemble bytes.
+ * After etc_solve (p0 must be NULL), etc_batch_results and etc_keff_batch
+ * report per RVE in input order; etc_get_solution and etc_grad write the RVEs
+ * back to back in input order (sum of their voxel counts, float64, user
+ * layout); etc_residual_history reports RVE 0.  etc_keff, etc_apply_A,
+ * etc_apply_Minv, etc_set_kernel_timer and etc_launch_info reject an
+ * ensemble plan (ETC_E_INVALID). */
+etc_status etc_setup_ensemble(const void* const* kappa, const int64_t* dims, int count, etc_dtype dt, etc_bc bc,
+                              int axis, const etc_options* opt, etc_plan** plan);
+etc_status etc_workspace_size_ensemble(const int64_t* dims, int count, etc_dtype dt, int axis, const etc_options* opt,
+                                       size_t* bytes);
+
 /* Per-instance passes, status and last relative residual of the last solve
  * (host arrays of nbatch entries; any may be NULL). */
 etc_status etc_batch_results(const etc_plan* plan, int* iters, int* status, double* relres);

@@ -23,7 +23,8 @@ __all__ = [
     "etc_get_solution", "etc_residual_history", "etc_apply_A", "etc_apply_Minv", "etc_set_kernel_timer",
     "etc_kernel_time", "etc_copy_f64", "etc_destroy", "etc_last_error", "etc_version", "Plan", "solve",
     "STATUS", "etc_grad", "keff", "etc_setup_batch", "etc_batch_results", "etc_keff_batch", "solve_batch",
-    "etc_solve_static", "STATIC_SCRATCH_BYTES",
+    "etc_solve_static", "STATIC_SCRATCH_BYTES", "etc_setup_ensemble", "etc_workspace_size_ensemble",
+    "solve_ensemble",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -120,6 +121,12 @@ _SYMBOLS = {
     "etc_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "etc_copy_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "etc_destroy": (None, [ctypes.c_void_p]),
+    "etc_setup_ensemble": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                          ctypes.c_int, _BC, ctypes.c_int, ctypes.POINTER(_Options),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "etc_workspace_size_ensemble": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                                   ctypes.c_int, ctypes.POINTER(_Options),
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
     "etc_solve_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC,
                                         ctypes.c_int, ctypes.POINTER(_Options), ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -398,18 +405,92 @@ def solve_batch(kappa, axis: int = 0, **kw) -> dict:
     return out
 
 
-def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_grad: bool = False,
-                   concurrent: bool = True, **kw) -> dict:
-    """K_eff of an ensemble of RVEs of mixed sizes.
+def etc_workspace_size_ensemble(shapes, dtype="float64", axis=0, **opts) -> int:
+    o = _options(**opts)
+    n = len(shapes)
+    dims = (ctypes.c_int64 * (3 * n))(*[int(d) for sh in shapes for d in sh])
+    out = ctypes.c_size_t(0)
+    _check(load_library().etc_workspace_size_ensemble(dims, n, _DTYPE[dtype], int(axis), ctypes.byref(o),
+                                                      ctypes.byref(out)))
+    return int(out.value)
 
-    RVEs of one shape are stacked into batch plans (at most ``max_batch_voxels``
-    voxels per plan), each solved with per-instance exit tests; results are
-    returned in input order.  With ``concurrent`` the plans run at the same
-    time, each on a stream of its own driven by a host thread (small batches
-    then share the device instead of running one after another).  With
-    ``want_grad`` the gradients dK/dkappa are returned too (one tensor per
-    RVE)."""
+
+def etc_setup_ensemble(kappas, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
+                       rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 20, poll_every: int = 8,
+                       kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, precond: str = "dct",
+                       use_graph: bool = False, autotune: bool = False) -> Plan:
+    """Mixed-size ensemble: a list of 3D tensors (one dtype, one device) solved
+    together, every kernel of a pass one launch for all of them.  Solutions
+    and gradients come back as one flat float64 tensor, the RVEs back to back
+    in input order (``plan.ensemble_shapes`` splits it)."""
     torch = _torch()
+    ks = list(kappas)
+    if not ks:
+        raise ValueError("an ensemble needs at least one RVE")
+    for k in ks:
+        if not isinstance(k, torch.Tensor) or k.dim() != 3 or k.device.type != "cuda":
+            raise ValueError("every RVE must be a 3D torch tensor on a GPU device")
+        if k.dtype not in (torch.float64, torch.float32) or k.dtype != ks[0].dtype or k.device != ks[0].device:
+            raise ValueError("every RVE must be float64 or float32, one dtype on one device")
+    ks = [k.contiguous() for k in ks]
+    dtype = "float64" if ks[0].dtype == torch.float64 else "float32"
+    device = ks[0].device
+    stream = torch.cuda.current_stream(device)
+    o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
+                 want_grad, precond, use_graph, autotune)
+    n = len(ks)
+    dims = (ctypes.c_int64 * (3 * n))(*[int(d) for k in ks for d in k.shape])
+    ptrs = (ctypes.c_void_p * n)(*[k.data_ptr() for k in ks])
+    nbytes = ctypes.c_size_t(0)
+    _check(load_library().etc_workspace_size_ensemble(dims, n, _DTYPE[dtype], int(axis), ctypes.byref(o),
+                                                      ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = int(nbytes.value)
+    h = ctypes.c_void_p(0)
+    _check(load_library().etc_setup_ensemble(ptrs, dims, n, _DTYPE[dtype], _BC(float(p_in), float(p_out)),
+                                             int(axis), ctypes.byref(o), ctypes.byref(h)))
+    total = sum(k.numel() for k in ks)
+    plan = Plan(h, ws, (total, 1, 1), int(axis), precision, device, stream)
+    plan.shape = (total,)
+    plan.nbatch = n
+    plan.ensemble_shapes = [tuple(k.shape) for k in ks]
+    return plan
+
+
+def _split_flat(flat, shapes):
+    out, off = [], 0
+    for sh in shapes:
+        v = math.prod(sh)
+        out.append(flat[off:off + v].view(sh))
+        off += v
+    return out
+
+
+def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_grad: bool = False,
+                   concurrent: bool = True, mode: str = "launch", **kw) -> dict:
+    """K_eff of an ensemble of RVEs of mixed sizes, results in input order.
+
+    mode "launch" (default): one ensemble plan (etc_setup_ensemble); every
+    kernel of a pass is one launch for all RVEs, each with its own exit test.
+    mode "plans": RVEs of one shape are stacked into batch plans (at most
+    ``max_batch_voxels`` voxels per plan); with ``concurrent`` the plans run at
+    the same time, each on a stream of its own driven by a host thread.
+    With ``want_grad`` the gradients dK/dkappa are returned too (one tensor
+    per RVE)."""
+    torch = _torch()
+    if mode == "launch":
+        plan = etc_setup_ensemble(kappas, axis, want_grad=want_grad, **kw)
+        etc_solve(plan)
+        out = etc_batch_results(plan)
+        out.update(etc_keff_batch(plan))
+        out["plans"] = 1
+        if want_grad:
+            out["grad"] = _split_flat(etc_grad(plan), plan.ensemble_shapes)
+        plan.close()
+        return out
+    if mode != "plans":
+        raise ValueError("mode must be 'launch' or 'plans'")
     buckets: dict = {}
     for i, k in enumerate(kappas):
         if not isinstance(k, torch.Tensor) or k.dim() != 3 or k.device.type != "cuda":

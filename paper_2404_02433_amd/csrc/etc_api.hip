@@ -140,6 +140,11 @@ struct etc_plan {
   };
   std::vector<GraphEntry> graphs;
   int tuned;  // 1: launch shapes chosen by the autotuner
+  // mixed-size ensemble: one batch plan per distinct shape (groups), all on
+  // this plan's stream and solved together by multi-group launches; empty
+  // for every other plan
+  std::vector<etc_plan*> groups;
+  std::vector<int> inst_group, inst_local;  // ensemble instance (input order) -> group, index in it
   // kernel timer
   int timer_id;
   std::vector<hipEvent_t> ev;
@@ -438,11 +443,14 @@ template <class S> struct Ops {
 
   // Canonical copies of instance `inst` (conductivity components, source)
   // and its family extrema into the first 12 * nStride partials.
-  static etc_status canon(etc_plan* P, const void* const comp_user[3], const double* source, int inst) {
+  // inst_src: this instance's own conductivity array (isotropic batches
+  // whose instances are not back to back), else nullptr
+  static etc_status canon(etc_plan* P, const void* const comp_user[3], const double* source, int inst,
+                          const void* inst_src = nullptr) {
     const int64_t off = (int64_t)inst * P->g.V;
     const size_t in_es = (P->in_dt == ETC_F64) ? sizeof(double) : sizeof(float);
     for (int c = 0; c < (P->ortho ? 3 : 1); ++c) {
-      const char* src = (const char*)comp_user[c] + (size_t)off * in_es;
+      const char* src = inst_src ? (const char*)inst_src : (const char*)comp_user[c] + (size_t)off * in_es;
       S* dst = (S*)P->kap_s[c] + off;
       double* dhi = P->kap_hi[c] ? P->kap_hi[c] + off : nullptr;
       etc_status s = (P->in_dt == ETC_F64) ? canon_one<double, S>(P, (const double*)src, dst, dhi)
@@ -979,6 +987,222 @@ template <class S> struct Ops {
     if (dot) return fin(P, FIN_ACC3, lc.nA, lc.nA);
     return ETC_OK;
   }
+
+  // ------------------------------------------ multi-group (ensemble) passes
+  // Every kernel of a pass is launched once for all groups of an ensemble
+  // plan E; group gi's blocks follow group gi-1's in the flat grid.
+  static void add_group(GroupMap& gm, int gi, dim3 grid, unsigned& total) {
+    gm.start[gi] = total;
+    gm.grid[gi] = grid;
+    total += grid.x * grid.y * grid.z;
+    gm.ng = gi + 1;
+    gm.start[gi + 1] = total;
+  }
+  // compile-time length a group's transforms run in a multi-group launch
+  // (0: the run-time-shaped kernel)
+  static int nc_rows(const etc_plan* P) {
+    int v = 0;
+    with_ct_len<T, true>(P->dpb.N, P->lc.rpb, [&](auto nc) { v = decltype(nc)::value; });
+    return multi_nc(v) ? v : 0;
+  }
+  static int nc_cols(const etc_plan* P) {
+    int v = 0;
+    with_ct_len<T, false>(P->dpa.N, P->lc.tb, [&](auto nc) { v = decltype(nc)::value; });
+    return multi_nc(v) ? v : 0;
+  }
+  static etc_status multi_lds(const etc_plan* E) {
+    size_t rows = 0, cols = 0;
+    for (const etc_plan* P : E->groups) {
+      rows = std::max(rows, P->lc.ldsRows);
+      cols = std::max(cols, P->lc.ldsCols);
+    }
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* fn, size_t bytes) {
+      if (e == hipSuccess && bytes > 65536) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    };
+    set((const void*)&k_rows_fwd_multi<S, T, 0>, rows);
+    set((const void*)&k_rows_fwd_multi<S, T, 1>, rows);
+    set((const void*)&k_rows_inv_multi<S, T, 1>, rows);
+    set((const void*)&k_cols_multi<S, T, -1>, cols);
+    set((const void*)&k_cols_multi<S, T, +1>, cols);
+    if (e != hipSuccess) return fail(ETC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    return ETC_OK;
+  }
+
+  static etc_status stencil_multi(etc_plan* E) {
+    GroupMap gm{};
+    StencilMulti<S, S, S> m{};
+    unsigned tot = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, P->lc.gridA, tot);
+      m.a[gi] = StencilArgs<S, S, S>{P->g, (const S*)P->w, kap(P), (const S*)P->kap_s[0], rhs(P), (S*)P->q,
+                                     P->partials, P->st, P->lc.kchunk};
+    }
+    constexpr int TBW = stencil_tbw(sizeof(S));
+    k_apply_A_iso_multi<S, false, S, TBW, kStencilTAH><<<tot, dim3(TBW, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
+    LAUNCHCHK("apply_A_multi");
+    return ETC_OK;
+  }
+
+  // mixed form: r = b - A p in float64 arithmetic where a refinement is due
+  template <class KT>
+  static etc_status residual_multi_kt(etc_plan* E) {
+    GroupMap gm{};
+    StencilMulti<S, double, KT> m{};
+    unsigned tot = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, P->lc.gridRes, tot);
+      const KT* ks = std::is_same<KT, double>::value ? (const KT*)(const void*)P->kap_hi[0] : (const KT*)P->kap_s[0];
+      m.a[gi] = StencilArgs<S, double, KT>{P->g, P->p, kap(P), ks, rhs(P), (S*)P->r, P->partials, P->st, P->lc.kchunk};
+    }
+    k_apply_A_iso_multi<S, true, KT, 64, kStencilTAH><<<tot, dim3(64, kStencilTAH / 4), 0, E->stream>>>(gm, m, 2);
+    LAUNCHCHK("residual_multi");
+    return ETC_OK;
+  }
+  static etc_status residual_multi(etc_plan* E) {
+    return E->groups[0]->kap_hi[0] ? residual_multi_kt<double>(E) : residual_multi_kt<S>(E);
+  }
+
+  // n(P): partial sums per instance of the reducing kernel just launched
+  template <class F>
+  static etc_status fin_multi(etc_plan* E, int op, F&& n) {
+    GroupMap gm{};
+    FinMulti m{};
+    unsigned tot = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, dim3(P->nseg, 1, 1), tot);
+      const int np = n(P);
+      m.a[gi] = FinArgs{P->partials, np, np, P->st, P->hist, P->hstride};
+    }
+    k_fin_multi<<<tot, 1024, 0, E->stream>>>(gm, m, op);
+    LAUNCHCHK("finalize_multi");
+    return ETC_OK;
+  }
+
+  template <int MODE>
+  static etc_status rows_fwd_multi(etc_plan* E, int gate) {
+    GroupMap gm{};
+    RowsMulti<S, T> m{};
+    unsigned tot = 0;
+    size_t lds = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, P->lc.gridRows, tot);
+      lds = std::max(lds, P->lc.ldsRows);
+      m.a[gi] = RowsArgs<S, T>{P->g, P->dpb, (const cx<T>*)P->tw_b, MODE == 1 ? nullptr : (const S*)P->r,
+                               (S*)P->t, P->lc.rpb, P->lc.nrows, MODE == 1 ? (S*)P->r : nullptr,
+                               MODE == 1 ? (const S*)P->q : nullptr, MODE == 1 ? P->partials : nullptr, P->st,
+                               nc_rows(P)};
+    }
+    k_rows_fwd_multi<S, T, MODE><<<tot, kThreads, lds, E->stream>>>(gm, m, gate);
+    LAUNCHCHK("rows_fwd_multi");
+    return ETC_OK;
+  }
+
+  static etc_status rows_inv_multi(etc_plan* E) {
+    GroupMap gm{};
+    RowsMulti<S, T> m{};
+    unsigned tot = 0;
+    size_t lds = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, P->lc.gridRows, tot);
+      lds = std::max(lds, P->lc.ldsRows);
+      m.a[gi] = RowsArgs<S, T>{P->g, P->dpb, (const cx<T>*)P->tw_b, (const S*)P->t, (S*)P->w, P->lc.rpb,
+                               P->lc.nrows, xsol(P), nullptr, nullptr, P->st, nc_rows(P)};
+    }
+    k_rows_inv_multi<S, T, 1><<<tot, kThreads, lds, E->stream>>>(gm, m, 1);
+    LAUNCHCHK("rows_inv_multi");
+    return ETC_OK;
+  }
+
+  template <int DIR>
+  static etc_status cols_multi(etc_plan* E) {
+    GroupMap gm{};
+    ColsMulti<S, T> m{};
+    unsigned tot = 0;
+    size_t lds = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, P->lc.gridCols, tot);
+      lds = std::max(lds, P->lc.ldsCols);
+      m.a[gi] = ColsArgs<S, T>{P->g, P->dpa, (const cx<T>*)P->tw_a, (S*)P->t, P->lc.tb, P->st, nc_cols(P)};
+    }
+    k_cols_multi<S, T, DIR><<<tot, E->groups[0]->lc.colThreads, lds, E->stream>>>(gm, m, 1);
+    LAUNCHCHK("cols_multi");
+    return ETC_OK;
+  }
+
+  static etc_status thomas_multi(etc_plan* E) {
+    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
+    GroupMap gm{};
+    ThomasMulti<S> m{};
+    unsigned tot = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      const LaunchCfg& lc = P->lc;
+      add_group(gm, gi, lc.gridThomas, tot);
+      // the variant the group's own plan launches (with_thomas)
+      int maxm = lc.maxm;
+      const bool exact = lc.Puse == kThomasP && P->g.nL == kThomasP * maxm &&
+                         (maxm == 16 || maxm == 8 || maxm == 5 || maxm == 4 || maxm == 3 || maxm == 2);
+      if (!exact) maxm = maxm <= 4 ? 4 : (maxm <= 8 ? 8 : 16);
+      m.a[gi] = ThomasArgs<S>{P->g, ref(P), (S*)P->t, lc.Puse, P->partials, P->st, lc.thomasTiles, lc.nThomas,
+                              thomas_variant(maxm, exact)};
+    }
+    k_thomas_multi<S, TB, kThomasP><<<tot, TB * kThomasP, 0, E->stream>>>(gm, m, 1);
+    LAUNCHCHK("thomas_multi");
+    return ETC_OK;
+  }
+
+  static etc_status flush_multi(etc_plan* E) {
+    GroupMap gm{};
+    FlushMulti m{};
+    unsigned tot = 0;
+    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+      etc_plan* P = E->groups[gi];
+      add_group(gm, gi, P->lc.gridStride, tot);
+      m.a[gi] = FlushArgs{P->g, P->p, (float*)P->dlt, (const float*)P->w, P->st};
+    }
+    k_flush_multi<<<tot, kThreads, 0, E->stream>>>(gm, m);
+    LAUNCHCHK("flush_multi");
+    return ETC_OK;
+  }
+
+  // One PCG pass (alg:pcg loop body) for every instance of every group.
+  static etc_status iteration_multi(etc_plan* E) {
+    etc_status s;
+    if ((s = stencil_multi(E))) return s;
+    if ((s = fin_multi(E, FIN_ALPHA, [](const etc_plan* P) { return P->lc.nA; }))) return s;
+    if ((s = rows_fwd_multi<1>(E, 1))) return s;
+    if ((s = fin_multi(E, FIN_RR, [](const etc_plan* P) { return P->lc.nRows; }))) return s;
+    if (E->prec == ETC_MIXED) {
+      if ((s = flush_multi(E))) return s;
+      if ((s = residual_multi(E))) return s;
+      if ((s = fin_multi(E, FIN_REFINE, [](const etc_plan* P) { return residual_parts(P); }))) return s;
+      if ((s = rows_fwd_multi<0>(E, 2))) return s;
+    }
+    if ((s = cols_multi<-1>(E))) return s;
+    if ((s = thomas_multi(E))) return s;
+    if ((s = fin_multi(E, FIN_BETA, [](const etc_plan* P) { return P->lc.nThomas; }))) return s;
+    if ((s = cols_multi<+1>(E))) return s;
+    return rows_inv_multi(E);
+  }
+
+  // dK/dkappa of one instance of a batch plan into `out` (user layout)
+  static etc_status grad_instance(etc_plan* P, int inst, double* out, double c) {
+    Geo g1 = P->g;
+    g1.nseg = 1;
+    const int64_t off = (int64_t)inst * P->g.V;
+    Kap<S> k = kap(P);
+    k.shift(off);
+    k_grad<S><<<dim3(P->lc.nStride, 1), kThreads, 0, P->stream>>>(g1, P->p + off, P->padj + off, k, c, P->axis, out);
+    LAUNCHCHK("grad");
+    return ETC_OK;
+  }
 };
 
 }  // namespace
@@ -1004,6 +1228,7 @@ void etc_options_default(etc_options* o) {
 }
 
 etc_status etc_launch_info(const etc_plan* P, int* kchunk, int* thomas_blocks, int* tuned) {
+  if (P && !P->groups.empty()) return fail(ETC_E_INVALID, "not defined for an ensemble plan (use the batch calls)");
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
   if (kchunk) *kchunk = P->lc.kchunk;
   if (thomas_blocks) *thomas_blocks = (int)P->lc.gridThomas.x;
@@ -1056,8 +1281,11 @@ etc_status etc_workspace_size_batch(const int64_t n[3], int nbatch, etc_dtype dt
 
 }  // extern "C"
 
+// inst_kappa: per-instance conductivity pointers of a batch whose instances
+// are not stored back to back (isotropic only), else nullptr
 static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t n[3], int nseg, etc_bc bc, int axis,
-                             const etc_options* opt, etc_plan** out, bool no_alloc = false) {
+                             const etc_options* opt, etc_plan** out, bool no_alloc = false,
+                             const void* const* inst_kappa = nullptr) {
   if (!out) return fail(ETC_E_INVALID, "plan is NULL");
   *out = nullptr;
   if (!pr) return fail(ETC_E_INVALID, "problem is NULL");
@@ -1241,8 +1469,8 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
     }
     std::vector<double> part((size_t)P->lc.nStride * 12);
     for (int inst = 0; inst < nseg; ++inst) {
-      s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source, inst)
-                                 : Ops<double>::canon(P, comp, pr->source, inst);
+      s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source, inst, inst_kappa ? inst_kappa[inst] : nullptr)
+                                 : Ops<double>::canon(P, comp, pr->source, inst, inst_kappa ? inst_kappa[inst] : nullptr);
       if (s) return bail(s);
       if (inst == 0 && (s = upload_tables())) return bail(s);
       if (hipMemcpyAsync(part.data(), P->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -1376,8 +1604,259 @@ etc_status etc_setup_batch(const void* kappa, etc_dtype dt, const int64_t n[3], 
   return setup_impl(&pr, dt, n, nbatch, bc, axis, opt, out);
 }
 
+// Groups of a mixed-size ensemble: the instances of each distinct shape, in
+// the order of first appearance, then sorted largest group first (its
+// blocks lead every multi-group launch); workspace ranges per group.
+struct EnsembleLayout {
+  std::vector<std::vector<int64_t>> dims;  // user dims per group
+  std::vector<std::vector<int>> members;   // instance indices per group
+  std::vector<int> inst_group, inst_local;
+  std::vector<size_t> ws_off, ws_size;
+  size_t total = 0;
+};
+
+static etc_status ensemble_layout(const int64_t* dims, int count, etc_dtype dt, int axis, const etc_options& o,
+                                  EnsembleLayout& L) {
+  if (!dims) return fail(ETC_E_INVALID, "dims is NULL");
+  if (count < 1 || count > 4096) return fail(ETC_E_INVALID, "count must be in 1..4096");
+  if (dt != ETC_F64 && dt != ETC_F32) return fail(ETC_E_INVALID, "bad dtype");
+  std::vector<std::vector<int64_t>> gd;
+  std::vector<std::vector<int>> gm;
+  for (int i = 0; i < count; ++i) {
+    const int64_t* n = dims + 3 * (size_t)i;
+    etc_status s = validate(n, axis, o);
+    if (s) return s;
+    if (n[axis] > kThomasP * 16)
+      return fail(ETC_E_UNSUPPORTED, "ensemble RVEs take load axes up to 512 voxels");
+    std::vector<int64_t> key(n, n + 3);
+    size_t gi = 0;
+    while (gi < gd.size() && gd[gi] != key) ++gi;
+    if (gi == gd.size()) {
+      gd.push_back(key);
+      gm.emplace_back();
+    }
+    gm[gi].push_back(i);
+  }
+  if ((int)gd.size() > kMaxGroups)
+    return fail(ETC_E_UNSUPPORTED, "an ensemble takes at most " + std::to_string(kMaxGroups) + " distinct RVE shapes");
+  std::vector<size_t> order(gd.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  auto voxels = [&](size_t g) { return gd[g][0] * gd[g][1] * gd[g][2] * (int64_t)gm[g].size(); };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return voxels(a) > voxels(b); });
+  L = EnsembleLayout{};
+  L.inst_group.assign(count, 0);
+  L.inst_local.assign(count, 0);
+  for (size_t k = 0; k < order.size(); ++k) {
+    const size_t g = order[k];
+    L.dims.push_back(gd[g]);
+    L.members.push_back(gm[g]);
+    for (size_t j = 0; j < gm[g].size(); ++j) {
+      L.inst_group[gm[g][j]] = (int)k;
+      L.inst_local[gm[g][j]] = (int)j;
+    }
+    const size_t sz = align_up(plan_sizes(gd[g].data(), axis, dt, o, ProblemShape{false, false, false},
+                                          (int)gm[g].size()).total);
+    L.ws_off.push_back(L.total);
+    L.ws_size.push_back(sz);
+    L.total += sz;
+  }
+  return ETC_OK;
+}
+
+// Captured passes of an ensemble plan (use_graph), keyed like a plan's own
+// graphs by the first group's solution buffer and the Dirichlet pair (the
+// adjoint solve swaps both).
+static etc_status ensemble_graph(etc_plan* E, hipGraphExec_t* out, hipStream_t* ls) {
+  hipStream_t cs = E->stream;
+  if (!cs) {
+    if (!E->cstream) HIPCHK(hipStreamCreate(&E->cstream));
+    cs = E->cstream;
+  }
+  *ls = cs;
+  etc_plan* G0 = E->groups[0];
+  for (auto& e : E->graphs)
+    if (e.p == G0->p && e.p_in == G0->g.p_in && e.p_out == G0->g.p_out) {
+      *out = e.exec;
+      return ETC_OK;
+    }
+  const hipStream_t saved = E->stream;
+  E->stream = cs;
+  etc_plan::GraphEntry e{G0->p, G0->g.p_in, G0->g.p_out, false, nullptr, nullptr};
+  etc_status s = ETC_OK;
+  hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (he == hipSuccess) {
+    for (int i = 0; i < E->opt.poll_every && s == ETC_OK; ++i)
+      s = (E->prec == ETC_MIXED) ? Ops<float>::iteration_multi(E) : Ops<double>::iteration_multi(E);
+    hipError_t he2 = hipStreamEndCapture(cs, &e.graph);
+    if (he2 != hipSuccess && s == ETC_OK)
+      s = fail(ETC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he2));
+  } else {
+    s = fail(ETC_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(he));
+  }
+  E->stream = saved;
+  if (s) {
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    return s;
+  }
+  if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(e.graph);
+    return fail(ETC_E_HIP, "hipGraphInstantiate failed");
+  }
+  E->graphs.push_back(e);
+  *out = e.exec;
+  return ETC_OK;
+}
+
+// PCG for every instance of every group of an ensemble plan: each kernel of
+// a pass is one launch for the whole ensemble; the host reads every group's
+// device state once per `poll_every` passes.
+static etc_status solve_ensemble(etc_plan* E, etc_result* res) {
+  etc_status s;
+  const bool mixed = E->prec == ETC_MIXED;
+  for (etc_plan* P : E->groups) {
+    if ((s = reset_state(P))) return s;
+    if ((s = mixed ? Ops<float>::init(P, nullptr) : Ops<double>::init(P, nullptr))) return s;
+  }
+  if ((s = mixed ? Ops<float>::multi_lds(E) : Ops<double>::multi_lds(E))) return s;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t gstream = nullptr;
+  if (E->opt.use_graph) {
+    if ((s = ensemble_graph(E, &exec, &gstream))) return s;
+    if (gstream != E->stream) HIPCHK(hipStreamSynchronize(E->stream));
+  }
+  int enq = 0;
+  const int chunk = E->opt.poll_every;
+  for (;;) {
+    for (etc_plan* P : E->groups)
+      HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(DevState) * P->nseg, hipMemcpyDeviceToHost, E->stream));
+    HIPCHK(hipStreamSynchronize(E->stream));
+    bool all_done = true;
+    for (etc_plan* P : E->groups)
+      for (int i = 0; i < P->nseg; ++i) all_done = all_done && P->st_host[i].done;
+    if (all_done || enq > E->opt.max_iter) break;
+    if (exec) {
+      HIPCHK(hipGraphLaunch(exec, gstream));
+    } else {
+      for (int i = 0; i < chunk; ++i)
+        if ((s = mixed ? Ops<float>::iteration_multi(E) : Ops<double>::iteration_multi(E))) return s;
+    }
+    enq += chunk;
+  }
+  for (etc_plan* P : E->groups)
+    if ((s = mixed ? Ops<float>::fixup(P) : Ops<double>::fixup(P))) return s;
+  HIPCHK(hipStreamSynchronize(E->stream));
+  int iters = 0, status = ST_OK;
+  for (etc_plan* P : E->groups) {
+    int gi = 0, gs = ST_OK;
+    for (int i = 0; i < P->nseg; ++i) {
+      const DevState& h = P->st_host[i];
+      gi = std::max(gi, h.iter);
+      const int st = h.done ? h.status : ST_NOT_CONVERGED;
+      if (st == ST_BREAKDOWN) gs = ST_BREAKDOWN;
+      else if (st == ST_NOT_CONVERGED && gs == ST_OK) gs = ST_NOT_CONVERGED;
+    }
+    P->last_iters = gi;
+    P->last_status = gs;
+    P->solved = gs != ST_BREAKDOWN;
+    iters = std::max(iters, gi);
+    if (gs == ST_BREAKDOWN) status = ST_BREAKDOWN;
+    else if (gs == ST_NOT_CONVERGED && status == ST_OK) status = ST_NOT_CONVERGED;
+  }
+  E->last_iters = iters;
+  E->last_status = status;
+  if (res) {
+    const etc_plan* P0 = E->groups[E->inst_group[0]];
+    const int j0 = E->inst_local[0];
+    res->iters = P0->st_host[j0].iter;
+    res->status = status;
+    res->relres = P0->st_host[j0].relres;
+    for (int i = 0; i < 5; ++i) res->kref[i] = P0->kref[(size_t)5 * j0 + i];
+    res->lambda_lo = P0->lam_lo[j0];
+    res->lambda_hi = P0->lam_hi[j0];
+  }
+  if (status == ST_BREAKDOWN) {
+    E->solved = false;
+    return fail(ETC_E_BREAKDOWN, "PCG breakdown (non-positive or non-finite scalar)");
+  }
+  E->solved = true;
+  if (status == ST_NOT_CONVERGED) {
+    g_err = "iteration cap reached";
+    return ETC_NOT_CONVERGED;
+  }
+  return ETC_OK;
+}
+
+etc_status etc_workspace_size_ensemble(const int64_t* dims, int count, etc_dtype dt, int axis, const etc_options* opt,
+                                       size_t* bytes) {
+  if (!bytes) return fail(ETC_E_INVALID, "bytes is NULL");
+  etc_options o;
+  if (opt) o = *opt;
+  else etc_options_default(&o);
+  EnsembleLayout L;
+  etc_status s = ensemble_layout(dims, count, dt, axis, o, L);
+  if (s) return s;
+  *bytes = L.total;
+  return ETC_OK;
+}
+
+etc_status etc_setup_ensemble(const void* const* kappa, const int64_t* dims, int count, etc_dtype dt, etc_bc bc,
+                              int axis, const etc_options* opt, etc_plan** out) {
+  if (!out) return fail(ETC_E_INVALID, "plan is NULL");
+  *out = nullptr;
+  if (!kappa) return fail(ETC_E_INVALID, "kappa is NULL");
+  etc_options o;
+  if (opt) o = *opt;
+  else etc_options_default(&o);
+  EnsembleLayout L;
+  etc_status s = ensemble_layout(dims, count, dt, axis, o, L);
+  if (s) return s;
+  for (int i = 0; i < count; ++i)
+    if (!kappa[i]) return fail(ETC_E_INVALID, "kappa[" + std::to_string(i) + "] is NULL");
+  if (o.workspace && o.workspace_bytes < L.total) return fail(ETC_E_NOMEM, "workspace smaller than etc_workspace_size_ensemble");
+  if (o.poll_every < 1) o.poll_every = 1;
+  etc_plan* E = new etc_plan();
+  E->opt = o;
+  E->axis = axis;
+  E->in_dt = dt;
+  E->prec = o.precision;
+  E->stream = (hipStream_t)o.stream;
+  E->nseg = count;
+  E->hstride = o.max_iter + 2;
+  E->own_ws = false;
+  E->solved = false;
+  for (size_t gi = 0; gi < L.dims.size(); ++gi) {
+    etc_options og = o;
+    og.use_graph = 0;  // the ensemble captures its own passes
+    if (o.workspace) {
+      og.workspace = (char*)o.workspace + L.ws_off[gi];
+      og.workspace_bytes = L.ws_size[gi];
+    }
+    std::vector<const void*> ptrs;
+    for (int i : L.members[gi]) ptrs.push_back(kappa[i]);
+    etc_problem pr;
+    std::memset(&pr, 0, sizeof(pr));
+    pr.kappa[0] = ptrs[0];
+    etc_plan* G = nullptr;
+    s = setup_impl(&pr, dt, L.dims[gi].data(), (int)ptrs.size(), bc, axis, &og, &G, false, ptrs.data());
+    if (s) {
+      const std::string msg = g_err;
+      etc_destroy(E);
+      return fail(s, msg);
+    }
+    E->groups.push_back(G);
+  }
+  E->inst_group = L.inst_group;
+  E->inst_local = L.inst_local;
+  *out = E;
+  return ETC_OK;
+}
+
 etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (!P->groups.empty()) {
+    if (p0) return fail(ETC_E_UNSUPPORTED, "an ensemble plan starts from p0 = 0");
+    return solve_ensemble(P, res);
+  }
   etc_status s = reset_state(P);
   if (s) return s;
   // kernel timer events
@@ -1469,6 +1948,15 @@ etc_status etc_solve(etc_plan* P, const double* p0, etc_result* res) {
 
 etc_status etc_batch_results(const etc_plan* P, int* iters, int* status, double* relres) {
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (!P->groups.empty()) {
+    for (size_t i = 0; i < P->inst_group.size(); ++i) {
+      const DevState& h = P->groups[P->inst_group[i]]->st_host[P->inst_local[i]];
+      if (iters) iters[i] = h.iter;
+      if (status) status[i] = h.done ? h.status : ST_NOT_CONVERGED;
+      if (relres) relres[i] = h.relres;
+    }
+    return ETC_OK;
+  }
   for (int i = 0; i < P->nseg; ++i) {
     const DevState& h = P->st_host[i];
     if (iters) iters[i] = h.iter;
@@ -1487,6 +1975,7 @@ static etc_status keff_all(etc_plan* P, bool energy) {
 
 etc_status etc_keff(etc_plan* P, double* k_out, double* k_in, double* k_energy) {
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
+  if (P && !P->groups.empty()) return fail(ETC_E_INVALID, "not defined for an ensemble plan (use the batch calls)");
   if (!k_out) return fail(ETC_E_INVALID, "k_out is NULL");
   etc_status s = keff_all(P, k_energy != nullptr);
   if (s) return s;
@@ -1502,6 +1991,22 @@ etc_status etc_keff(etc_plan* P, double* k_out, double* k_in, double* k_energy) 
 etc_status etc_keff_batch(etc_plan* P, double* k_out, double* k_in) {
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
   if (!k_out) return fail(ETC_E_INVALID, "k_out is NULL");
+  if (!P->groups.empty()) {
+    if (!P->solved) return fail(ETC_E_STATE, "etc_keff_batch before a successful etc_solve");
+    for (etc_plan* G : P->groups) {
+      etc_status s = keff_all(G, false);
+      if (s) return s;
+    }
+    for (size_t i = 0; i < P->inst_group.size(); ++i) {
+      const etc_plan* G = P->groups[P->inst_group[i]];
+      const Geo& g = G->g;
+      const double scale = (double)g.nL / ((double)g.na * (double)g.nb * (g.p_in - g.p_out));
+      const DevState& h = G->st_host[P->inst_local[i]];
+      k_out[i] = scale * h.k_acc[0];
+      if (k_in) k_in[i] = scale * h.k_acc[1];
+    }
+    return ETC_OK;
+  }
   etc_status s = keff_all(P, false);
   if (s) return s;
   const Geo& g = P->g;
@@ -1513,27 +2018,57 @@ etc_status etc_keff_batch(etc_plan* P, double* k_out, double* k_in) {
   return ETC_OK;
 }
 
+// user-layout copy of instance `inst` of a (batch) plan's canonical vector
+static etc_status decanon_instance(const etc_plan* P, const double* vec, int inst, double* dst) {
+  Geo g = P->g;
+  g.nseg = 1;
+  const double* src = vec + (int64_t)inst * g.V;
+  if (P->axis == 2) {
+    dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
+    k_decanon_axis2<<<grid, dim3(32, 8), 0, P->stream>>>(src, dst, g);
+  } else {
+    k_decanon_rows<<<P->lc.nStride, kThreads, 0, P->stream>>>(src, dst, P->axis, g);
+  }
+  LAUNCHCHK("decanon");
+  return ETC_OK;
+}
+
 etc_status etc_get_solution(const etc_plan* P, double* p) {
   if (!P || !p) return fail(ETC_E_INVALID, "NULL argument");
   if (!P->solved) return fail(ETC_E_STATE, "etc_get_solution before a successful etc_solve");
-  Geo g = P->g;
-  g.nseg = 1;
-  for (int inst = 0; inst < P->nseg; ++inst) {
-    const double* src = P->p + (int64_t)inst * g.V;
-    double* dst = p + (int64_t)inst * g.V;
-    if (P->axis == 2) {
-      dim3 grid((g.nL + 31) / 32, (g.nb + 31) / 32, g.na);
-      k_decanon_axis2<<<grid, dim3(32, 8), 0, P->stream>>>(src, dst, g);
-    } else {
-      k_decanon_rows<<<P->lc.nStride, kThreads, 0, P->stream>>>(src, dst, P->axis, g);
+  if (!P->groups.empty()) {
+    int64_t off = 0;
+    for (size_t i = 0; i < P->inst_group.size(); ++i) {
+      const etc_plan* G = P->groups[P->inst_group[i]];
+      etc_status s = decanon_instance(G, G->p, P->inst_local[i], p + off);
+      if (s) return s;
+      off += G->g.V;
     }
-    LAUNCHCHK("decanon");
+    return ETC_OK;
+  }
+  for (int inst = 0; inst < P->nseg; ++inst) {
+    etc_status s = decanon_instance(P, P->p, inst, p + (int64_t)inst * P->g.V);
+    if (s) return s;
   }
   return ETC_OK;
 }
 
 etc_status etc_residual_history(const etc_plan* P, double* hist, int cap, int* count) {
   if (!P || !hist || !count) return fail(ETC_E_INVALID, "NULL argument");
+  if (!P->groups.empty()) {
+    // instance 0 of the ensemble (input order)
+    const etc_plan* G = P->groups[P->inst_group[0]];
+    const int j = P->inst_local[0];
+    int n = std::min(cap, G->st_host[j].iter + 1);
+    if (n < 0) n = 0;
+    if (n > 0) {
+      HIPCHK(hipMemcpyAsync(hist, G->hist + (int64_t)j * G->hstride, n * sizeof(double), hipMemcpyDeviceToHost,
+                            G->stream));
+      HIPCHK(hipStreamSynchronize(G->stream));
+    }
+    *count = n;
+    return ETC_OK;
+  }
   int n = std::min(cap, P->st_host[0].iter + 1);
   if (n < 0) n = 0;
   if (n > 0) {
@@ -1544,8 +2079,52 @@ etc_status etc_residual_history(const etc_plan* P, double* hist, int cap, int* c
   return ETC_OK;
 }
 
+static etc_status grad_ensemble(etc_plan* E, double* out) {
+  for (etc_plan* G : E->groups)
+    if (!G->padj) return fail(ETC_E_STATE, "etc_grad needs a plan made with want_grad = 1");
+  if (!E->solved) return fail(ETC_E_STATE, "etc_grad before a successful etc_solve");
+  // adjoint solves of every instance together: Dirichlet pair (0, 1),
+  // solutions into padj
+  struct Saved { Geo g; int iters, status; std::vector<DevState> st; };
+  std::vector<Saved> sv;
+  for (etc_plan* G : E->groups) {
+    sv.push_back(Saved{G->g, G->last_iters, G->last_status, std::vector<DevState>(G->st_host, G->st_host + G->nseg)});
+    std::swap(G->p, G->padj);
+    G->g.p_in = 0.0;
+    G->g.p_out = 1.0;
+  }
+  const int iters0 = E->last_iters, status0 = E->last_status;
+  etc_status s = solve_ensemble(E, nullptr);
+  for (size_t gi = 0; gi < E->groups.size(); ++gi) {
+    etc_plan* G = E->groups[gi];
+    std::swap(G->p, G->padj);
+    G->g = sv[gi].g;
+    G->last_iters = sv[gi].iters;
+    G->last_status = sv[gi].status;
+    std::copy(sv[gi].st.begin(), sv[gi].st.end(), G->st_host);
+    G->solved = true;
+  }
+  E->last_iters = iters0;
+  E->last_status = status0;
+  E->solved = true;
+  if (s != ETC_OK && s != ETC_NOT_CONVERGED) return s;
+  int64_t off = 0;
+  for (size_t i = 0; i < E->inst_group.size(); ++i) {
+    etc_plan* G = E->groups[E->inst_group[i]];
+    const Geo& g = G->g;
+    const double c = (double)g.nL / ((double)g.na * (double)g.nb * (g.p_in - g.p_out));
+    s = (G->prec == ETC_MIXED) ? Ops<float>::grad_instance(G, E->inst_local[i], out + off, c)
+                               : Ops<double>::grad_instance(G, E->inst_local[i], out + off, c);
+    if (s) return s;
+    off += g.V;
+  }
+  HIPCHK(hipStreamSynchronize(E->stream));
+  return ETC_OK;
+}
+
 etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
   if (!P || !dk_dkappa) return fail(ETC_E_INVALID, "NULL argument");
+  if (!P->groups.empty()) return grad_ensemble(P, dk_dkappa);
   if (!P->padj) return fail(ETC_E_STATE, "etc_grad needs a plan made with want_grad = 1");
   if (!P->solved) return fail(ETC_E_STATE, "etc_grad before a successful etc_solve");
   // adjoint solve: the primal system with Dirichlet pair (0, 1), solution into padj
@@ -1574,6 +2153,7 @@ etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
 }
 
 etc_status etc_apply_A(etc_plan* P, const void* x, void* y, double* xAx) {
+  if (P && !P->groups.empty()) return fail(ETC_E_INVALID, "not defined for an ensemble plan (use the batch calls)");
   if (!P || !x || !y) return fail(ETC_E_INVALID, "NULL argument");
   if (x == y) return fail(ETC_E_INVALID, "x and y must not alias");
   etc_status s = (P->prec == ETC_MIXED) ? Ops<float>::apply_A(P, x, y, xAx != nullptr)
@@ -1589,6 +2169,7 @@ etc_status etc_apply_A(etc_plan* P, const void* x, void* y, double* xAx) {
 }
 
 etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
+  if (P && !P->groups.empty()) return fail(ETC_E_INVALID, "not defined for an ensemble plan (use the batch calls)");
   if (!P || !r || !z) return fail(ETC_E_INVALID, "NULL argument");
   if (r == z) return fail(ETC_E_INVALID, "r and z must not alias");
   if (P->opt.precond == ETC_PC_NONE) {
@@ -1609,6 +2190,7 @@ etc_status etc_apply_Minv(etc_plan* P, const void* r, void* z, double* rz) {
 }
 
 etc_status etc_set_kernel_timer(etc_plan* P, int kernel_id) {
+  if (P && !P->groups.empty()) return fail(ETC_E_INVALID, "not defined for an ensemble plan (use the batch calls)");
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
   if (kernel_id < 0 || kernel_id > 6) return fail(ETC_E_INVALID, "kernel_id must be 0..6");
   P->timer_id = kernel_id;
@@ -1709,6 +2291,8 @@ etc_status etc_solve_static(const void* kappa, etc_dtype dt, const int64_t n[3],
 void etc_destroy(etc_plan* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->stream);
+  for (etc_plan* G : P->groups) etc_destroy(G);
+  P->groups.clear();
   for (auto& e : P->graphs) {
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
     if (e.graph) (void)hipGraphDestroy(e.graph);

@@ -76,6 +76,29 @@ __device__ __forceinline__ int flat_block() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
+// Block index and grid seen by a kernel body.  HwGrid: the launch's own
+// (the hardware registers, read where used).  SubGrid: one group's share of
+// a launch that covers several groups, each with a grid of its own.
+struct HwGrid {
+  __device__ __forceinline__ unsigned bx() const { return blockIdx.x; }
+  __device__ __forceinline__ unsigned by() const { return blockIdx.y; }
+  __device__ __forceinline__ unsigned bz() const { return blockIdx.z; }
+  __device__ __forceinline__ unsigned gx() const { return gridDim.x; }
+  __device__ __forceinline__ unsigned gy() const { return gridDim.y; }
+  __device__ __forceinline__ unsigned gz() const { return gridDim.z; }
+  __device__ __forceinline__ int flat() const { return flat_block(); }
+};
+struct SubGrid {
+  dim3 b, g;
+  __device__ __forceinline__ unsigned bx() const { return b.x; }
+  __device__ __forceinline__ unsigned by() const { return b.y; }
+  __device__ __forceinline__ unsigned bz() const { return b.z; }
+  __device__ __forceinline__ unsigned gx() const { return g.x; }
+  __device__ __forceinline__ unsigned gy() const { return g.y; }
+  __device__ __forceinline__ unsigned gz() const { return g.z; }
+  __device__ __forceinline__ int flat() const { return (int)(b.x + g.x * (b.y + g.y * b.z)); }
+};
+
 // Work-groups are dealt to the 8 XCDs round-robin by flat id.  Renumber so
 // that each XCD receives one contiguous range of tiles: tiles that share halo
 // lines then run on the same XCD at about the same time and meet in its L2.

@@ -38,7 +38,7 @@ template <class S> struct Kap {
   __device__ __forceinline__ double dA(int64_t i) const { return hA ? hA[i] : (double)A[i]; }
   __device__ __forceinline__ double dB(int64_t i) const { return hB ? hB[i] : (double)B[i]; }
   // view of instance s of a batch (instances are V voxels apart)
-  __device__ __forceinline__ void shift(int64_t off) {
+  __host__ __device__ __forceinline__ void shift(int64_t off) {
     L += off;
     A += off;
     B += off;
@@ -444,15 +444,15 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
 // RES = true: the float64 true residual r = b - A p of the mixed form (p
 // float64, kappa read as KT, arithmetic in C = double, r stored as S, partial
 // ||r||^2); RES = false: q = A w with the partial w . q, all in S.
-template <class S, bool RES, class KT, int TBW, int TAH>
-__global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso(Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
+template <class S, bool RES, class KT, int TBW, int TAH, class BG>
+__device__ __forceinline__ void k_apply_A_iso_body(const BG bg, Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
                                                      Kap<S> kp, const KT* __restrict__ ks, Rhs rh,
                                                      S* __restrict__ q, double* __restrict__ partials,
                                                      const DevState* __restrict__ st, int gate, int kchunk) {
   using C = typename std::conditional<RES, double, S>::type;
-  const int ntile = gridDim.x * gridDim.y * gridDim.z;
-  const int tile = xcd_tile(flat_block(), ntile);
-  const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
+  const int ntile = bg.gx() * bg.gy() * bg.gz();
+  const int tile = xcd_tile(bg.flat(), ntile);
+  const int bx = tile % bg.gx(), by = (tile / bg.gx()) % bg.gy(), bz = tile / (bg.gx() * bg.gy());
   const int nch = (g.nL + kchunk - 1) / kchunk;
   const int inst = bz / nch, chunk = bz - inst * nch;
   if (st) st += inst;
@@ -613,6 +613,14 @@ __global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso(Geo g, const type
   }
 }
 
+template <class S, bool RES, class KT, int TBW, int TAH>
+__global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso(Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
+                                                     Kap<S> kp, const KT* __restrict__ ks, Rhs rh,
+                                                     S* __restrict__ q, double* __restrict__ partials,
+                                                     const DevState* __restrict__ st, int gate, int kchunk) {
+  k_apply_A_iso_body<S, RES, KT, TBW, TAH, HwGrid>(HwGrid{}, g, w, kp, ks, rh, q, partials, st, gate, kchunk);
+}
+
 // r = b - A p in double arithmetic (p double, kappa at its input precision),
 // stored at S precision, with the partial ||r||^2, for orthotropic kappa (the
 // isotropic residual is k_apply_A_iso<S, true>).  Columns of 64 b x 4 a
@@ -735,24 +743,24 @@ template <class S> __device__ __forceinline__ void st16(S* p, const V16<S>& x) {
 // MODE 0: t = DCT_b(src).  MODE 1 (fused PCG update): r -= alpha q, partial
 // ||r||^2, t = DCT_b(r).  (The solution update x += alpha w is done by the
 // backward row transform, which reads w anyway.)
-template <class S, class T, int MODE, int NC = 0>
-__global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
+template <class S, class T, int MODE, int NC, class BG>
+__device__ __forceinline__ void k_rows_fwd_body(const BG bg, Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
                                                   S* __restrict__ r, const S* __restrict__ q,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
                                                   int gate) {
   using Sh = DctShape<T, NC>;
-  // instance blockIdx.y of a batch
-  if (st) st += blockIdx.y;
+  // instance bg.by() of a batch
+  if (st) st += bg.by();
   if (gated_out(st, gate)) return;
   {
-    const int64_t off = (int64_t)blockIdx.y * g.V;
+    const int64_t off = (int64_t)bg.by() * g.V;
     if (src) src += off;
     dst += off;
     if (MODE == 1) {
       r += off;
       q += off;
-      partials += (int64_t)blockIdx.y * gridDim.x;
+      partials += (int64_t)bg.by() * bg.gx();
     }
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -765,7 +773,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
   const bool fft = Sh::ct ? true : (dp.fft != 0);
   const int ls = Sh::ct ? Sh::ls : dp.lstride;
   const int rpbv = Sh::ct ? Sh::rows : rpb;
-  const int64_t row0 = (int64_t)blockIdx.x * rpbv;
+  const int64_t row0 = (int64_t)bg.bx() * rpbv;
   const int lines = (int)min((int64_t)rpbv, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
   const int total = lines * N;
@@ -879,8 +887,17 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
   }
   if (MODE == 1) {
     const double s = block_sum(acc, red);
-    if (tid == 0) partials[blockIdx.x] = s;
+    if (tid == 0) partials[bg.bx()] = s;
   }
+}
+
+template <class S, class T, int MODE, int NC = 0>
+__global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
+                                                  const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
+                                                  S* __restrict__ r, const S* __restrict__ q,
+                                                  double* __restrict__ partials, const DevState* __restrict__ st,
+                                                  int gate) {
+  k_rows_fwd_body<S, T, MODE, NC, HwGrid>(HwGrid{}, g, dp, tw, src, dst, rpb, nrows, r, q, partials, st, gate);
 }
 
 // Inverse along rows.  MODE 0: dst = DCT_b^{-1}(src).  MODE 1: dst holds w on
@@ -888,15 +905,15 @@ __global__ __launch_bounds__(256) void k_rows_fwd(Geo g, DctPlan dp, const cx<T>
 // refinement already folded it into p), then w = z + beta w with
 // z = DCT_b^{-1}(src) (never stored).  x is the solution p in the FP64 form
 // and the float32 increment since the last refinement in the mixed form.
-template <class S, class T, int MODE, int NC = 0>
-__global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
+template <class S, class T, int MODE, int NC, class BG>
+__device__ __forceinline__ void k_rows_inv_body(const BG bg, Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
                                                   const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
                                                   S* __restrict__ xs, const DevState* __restrict__ st, int gate) {
   using Sh = DctShape<T, NC>;
-  if (st) st += blockIdx.y;
+  if (st) st += bg.by();
   if (gated_out(st, gate)) return;
   {
-    const int64_t off = (int64_t)blockIdx.y * g.V;
+    const int64_t off = (int64_t)bg.by() * g.V;
     src += off;
     dst += off;
     if (MODE == 1) xs += off;
@@ -910,7 +927,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
   const bool fft = Sh::ct ? true : (dp.fft != 0);
   const int ls = Sh::ct ? Sh::ls : dp.lstride;
   const int rpbv = Sh::ct ? Sh::rows : rpb;
-  const int64_t row0 = (int64_t)blockIdx.x * rpbv;
+  const int64_t row0 = (int64_t)bg.bx() * rpbv;
   const int lines = (int)min((int64_t)rpbv, (int64_t)nrows - row0);
   const int64_t base = row0 * N;
   const int total = lines * N;
@@ -1050,20 +1067,27 @@ __global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>
   }
 }
 
+template <class S, class T, int MODE, int NC = 0>
+__global__ __launch_bounds__(256) void k_rows_inv(Geo g, DctPlan dp, const cx<T>* __restrict__ tw,
+                                                  const S* __restrict__ src, S* __restrict__ dst, int rpb, int nrows,
+                                                  S* __restrict__ xs, const DevState* __restrict__ st, int gate) {
+  k_rows_inv_body<S, T, MODE, NC, HwGrid>(HwGrid{}, g, dp, tw, src, dst, rpb, nrows, xs, st, gate);
+}
+
 // ========================================================= DCT along columns
 // Strided axis a, in place.  A block owns `tb` adjacent b columns of one
 // plane: every LDS line is one column (length na).  Element e
 // of a block is (row n, column c) = (e / tb, e % tb); columns beyond the
 // right edge of the plane are skipped.
-template <class S, class T, int DIR, int NC = 0>
-__global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
+template <class S, class T, int DIR, int NC, class BG>
+__device__ __forceinline__ void k_cols_body(const BG bg, Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
                                               int tb, const DevState* __restrict__ st, int gate) {
   using Sh = DctShape<T, NC>;
   // tile (column block bx, global plane) with tiles renumbered per XCD so
   // that tiles sharing 128-byte lines run on one XCD together; instances of a
   // batch hold nL planes each
-  const int tile = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const int bx = tile % gridDim.x, plane = tile / gridDim.x;
+  const int tile = xcd_tile(bg.bx() + bg.gx() * bg.by(), bg.gx() * bg.gy());
+  const int bx = tile % bg.gx(), plane = tile / bg.gx();
   if (st) st += plane / g.nL;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1179,6 +1203,12 @@ __global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __
       }
     }
   }
+}
+
+template <class S, class T, int DIR, int NC = 0>
+__global__ __launch_bounds__(512) void k_cols(Geo g, DctPlan dp, const cx<T>* __restrict__ tw, S* __restrict__ data,
+                                              int tb, const DevState* __restrict__ st, int gate) {
+  k_cols_body<S, T, DIR, NC, HwGrid>(HwGrid{}, g, dp, tw, data, tb, st, gate);
 }
 
 // Persistent column transforms (compile-time lengths, whole tiles; a batch
@@ -1407,18 +1437,16 @@ __device__ __forceinline__ double neumann_lambda(int k, double step) {
 // stores are issued, and the shift needs no load: a wait placed after the
 // stores would also wait for them to drain.  EXACT: nL = P * MAXM (every
 // partition has MAXM rows), which removes the ragged-length guards.
-template <class S, int TB, int P, int MAXM, bool EXACT, bool PF = ((EXACT && sizeof(S) == 4) || MAXM <= 8)>
-__global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
+template <class S, int TB, int P, int MAXM, bool EXACT, bool PF, class BG>
+__device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
-                                                  int gate, int ntx, int ntiles) {
-  // instance blockIdx.z of a batch
-  if (st) st += blockIdx.z;
+                                                  int gate, int ntx, int ntiles, double (&sh)[6][P][TB], double* red) {
+  // instance bg.bz() of a batch
+  if (st) st += bg.bz();
   if (gated_out(st, gate)) return;
-  t += (int64_t)blockIdx.z * g.V;
-  if (partials) partials += (int64_t)blockIdx.z * ntiles;
-  const double* kr = rm.kref + 5 * blockIdx.z;
-  __shared__ double sh[6][P][TB];  // phase 1: yF yL m11 mLL m1L ts; reduction: L U r 1/B; x
-  __shared__ double red[16];
+  t += (int64_t)bg.bz() * g.V;
+  if (partials) partials += (int64_t)bg.bz() * ntiles;
+  const double* kr = rm.kref + 5 * bg.bz();
   const int tid = threadIdx.x;
   const int l = tid % TB, p = tid / TB;
   const int nL = g.nL;
@@ -1456,7 +1484,7 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
   // tiles of one round are renumbered so that each XCD holds a contiguous
   // range (adjacent tiles share 128-byte lines when TB * sizeof(S) < 128)
   S cur[MAXM], cur_s = S(0);
-  int tile = blockIdx.x;
+  int tile = bg.bx();
   if (PF && tile < ntiles) {
     load(tile, cur, cur_s);
     // wait for the first tile here, outside the loop, so that the loop head
@@ -1465,7 +1493,7 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
     for (int j = 0; j < MAXM; ++j) asm volatile("" ::"v"(cur[j]));
     asm volatile("" ::"v"(cur_s));
   }
-  for (; tile < ntiles; tile += gridDim.x) {
+  for (; tile < ntiles; tile += bg.gx()) {
     const int bm = (tile % ntx) * TB + l, am = tile / ntx;
     const bool line_ok = bm < g.nb;
     const bool active = line_ok && pok;
@@ -1480,7 +1508,7 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
       // this tile's rows arrived before the loop head (first tile) or were
       // taken before the previous tile's stores; the shift is in registers
       asm volatile("" ::"v"(Dint));
-      const int tn = tile + gridDim.x;
+      const int tn = tile + bg.gx();
       if (tn < ntiles) load(tn, nxt, nxt_s);
     } else {
       load(tile, cur, cur_s);
@@ -1637,6 +1665,15 @@ __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __r
   }
 }
 
+template <class S, int TB, int P, int MAXM, bool EXACT, bool PF = ((EXACT && sizeof(S) == 4) || MAXM <= 8)>
+__global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
+                                                  double* __restrict__ partials, const DevState* __restrict__ st,
+                                                  int gate, int ntx, int ntiles) {
+  __shared__ double sh[6][P][TB];  // phase 1: yF yL m11 mLL m1L ts; reduction: L U r 1/B; x
+  __shared__ double red[16];
+  k_thomas_body<S, TB, P, MAXM, EXACT, PF, HwGrid>(HwGrid{}, g, rm, t, Puse, partials, st, gate, ntx, ntiles, sh, red);
+}
+
 
 // ================================================================ finalize
 enum FinOp { FIN_BNORM = 0, FIN_RHO0, FIN_ALPHA, FIN_RR, FIN_REFINE, FIN_BETA, FIN_RR0, FIN_ACC0, FIN_ACC1, FIN_ACC2, FIN_ACC3 };
@@ -1645,12 +1682,13 @@ enum FinOp { FIN_BNORM = 0, FIN_RHO0, FIN_ALPHA, FIN_RR, FIN_REFINE, FIN_BETA, F
 // scalar step of the iteration to the device state.
 // Block s handles instance s of a batch: partials + s * pstride, state s,
 // history row s (hstride entries).
-__global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__ partials, int n, int64_t pstride,
+template <class BG>
+__device__ __forceinline__ void k_fin_body(const BG bg, int op, const double* __restrict__ partials, int n, int64_t pstride,
                                               DevState* st, double* __restrict__ hist, int hstride) {
   __shared__ double red[16];
-  partials += (int64_t)blockIdx.x * pstride;
-  st += blockIdx.x;
-  hist += (int64_t)blockIdx.x * hstride;
+  partials += (int64_t)bg.bx() * pstride;
+  st += bg.bx();
+  hist += (int64_t)bg.bx() * hstride;
   if (op == FIN_REFINE) {
     if (st->done || !st->refine) return;
   } else if (op == FIN_ALPHA || op == FIN_RR || op == FIN_BETA || op == FIN_RHO0) {
@@ -1760,6 +1798,11 @@ __global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__
     }
     default: st->k_acc[op - FIN_ACC0] = s; break;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_fin(int op, const double* __restrict__ partials, int n, int64_t pstride,
+                                              DevState* st, double* __restrict__ hist, int hstride) {
+  k_fin_body<HwGrid>(HwGrid{}, op, partials, n, pstride, st, hist, hstride);
 }
 
 // ===================================================================== K_eff
@@ -1934,23 +1977,29 @@ __global__ __launch_bounds__(256) void k_dir_plain(Geo g, const S* __restrict__ 
 }
 
 // Mixed form, at a refinement: p += increment, increment = 0 (float64 p).
-__global__ __launch_bounds__(256) void k_flush(Geo g, double* __restrict__ p, float* __restrict__ dlt,
+template <class BG>
+__device__ __forceinline__ void k_flush_body(const BG bg, Geo g, double* __restrict__ p, float* __restrict__ dlt,
                                                const float* __restrict__ w, const DevState* __restrict__ st) {
-  st += blockIdx.y;
+  st += bg.by();
   if (st->done || !st->refine) return;
-  p += (int64_t)blockIdx.y * g.V;
-  dlt += (int64_t)blockIdx.y * g.V;
-  if (w) w += (int64_t)blockIdx.y * g.V;
+  p += (int64_t)bg.by() * g.V;
+  dlt += (int64_t)bg.by() * g.V;
+  if (w) w += (int64_t)bg.by() * g.V;
   // w given: this pass's alpha w is folded in here too (the backward row
   // transform then skips it)
   const double alpha = w ? st->alpha : 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.V; i += stride) {
+  const int64_t stride = (int64_t)bg.gx() * blockDim.x;
+  for (int64_t i = (int64_t)bg.bx() * blockDim.x + threadIdx.x; i < g.V; i += stride) {
     double v = p[i] + (double)dlt[i];
     if (w) v += alpha * (double)w[i];
     p[i] = v;
     dlt[i] = 0.0f;
   }
+}
+
+__global__ __launch_bounds__(256) void k_flush(Geo g, double* __restrict__ p, float* __restrict__ dlt,
+                                               const float* __restrict__ w, const DevState* __restrict__ st) {
+  k_flush_body<HwGrid>(HwGrid{}, g, p, dlt, w, st);
 }
 
 // x += alpha w for the instances whose last pass ended before its backward
@@ -1986,6 +2035,200 @@ __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src, do
       if (i0 + u * blockDim.x < nv) d2[i0 + u * blockDim.x] = v[u];
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+}
+
+// ================================================= multi-group (ensemble) launches
+// An ensemble of RVEs of several sizes keeps one batch of same-size RVEs per
+// size (a group).  Each kernel of a pass is then launched once for the whole
+// ensemble: the flat block index selects the group and a block of that
+// group's own grid, and the group's arguments (geometry, buffers, transform
+// plan, device state) come from a table in the kernel arguments.  The body
+// that runs is the single-group kernel's, with the compile-time variant the
+// group would use on its own (DCT length, partition length).
+constexpr int kMaxGroups = 8;
+
+struct GroupMap {
+  int ng;
+  unsigned start[kMaxGroups + 1];  // first flat block of each group; start[ng] = total
+  dim3 grid[kMaxGroups];           // each group's own grid
+  __device__ __forceinline__ int find(SubGrid& sg) const {
+    const unsigned b = blockIdx.x;
+    int gi = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxGroups; ++i) gi = (i < ng && b >= start[i]) ? i : gi;
+    const unsigned local = b - start[gi];
+    const dim3 gd = grid[gi];
+    sg.b = dim3(local % gd.x, (local / gd.x) % gd.y, local / (gd.x * gd.y));
+    sg.g = gd;
+    return gi;
+  }
+};
+
+template <class S, class W, class KT> struct StencilArgs {
+  Geo g;
+  const W* w;
+  Kap<S> kp;
+  const KT* ks;
+  Rhs rh;
+  S* q;
+  double* partials;
+  const DevState* st;
+  int kchunk;
+};
+template <class S, class W, class KT> struct StencilMulti { StencilArgs<S, W, KT> a[kMaxGroups]; };
+
+template <class S, bool RES, class KT, int TBW, int TAH>
+__global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso_multi(
+    GroupMap gm, StencilMulti<S, typename std::conditional<RES, double, S>::type, KT> m, int gate) {
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  k_apply_A_iso_body<S, RES, KT, TBW, TAH, SubGrid>(sg, x.g, x.w, x.kp, x.ks, x.rh, x.q, x.partials, x.st, gate,
+                                                   x.kchunk);
+}
+
+template <class S, class T> struct RowsArgs {
+  Geo g;
+  DctPlan dp;
+  const cx<T>* tw;
+  const S* src;
+  S* dst;
+  int rpb, nrows;
+  S* aux;            // forward: r (MODE 1); backward: the solution accumulator
+  const S* q;
+  double* partials;
+  const DevState* st;
+  int nc;            // compile-time length of the group's row kernels (0: run-time shaped)
+};
+template <class S, class T> struct RowsMulti { RowsArgs<S, T> a[kMaxGroups]; };
+
+// Calls f(std::integral_constant<int, NC>) for the ensemble lengths with
+// compile-time kernels (up to 160: the longer ones would raise the register
+// count of every multi-group launch), else with NC = 0 (run-time shaped).
+__host__ __device__ constexpr bool multi_nc(int nc) { return nc == 160 || nc == 128 || nc == 96 || nc == 64 || nc == 48; }
+template <class F> __device__ __forceinline__ void with_nc(int nc, F&& f) {
+  switch (nc) {
+    case 160: f(std::integral_constant<int, 160>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 96: f(std::integral_constant<int, 96>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 48: f(std::integral_constant<int, 48>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+  }
+}
+
+template <class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_rows_fwd_multi(GroupMap gm, RowsMulti<S, T> m, int gate) {
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  with_nc(x.nc, [&](auto nc) {
+    k_rows_fwd_body<S, T, MODE, decltype(nc)::value, SubGrid>(sg, x.g, x.dp, x.tw, x.src, x.dst, x.rpb, x.nrows,
+                                                                x.aux, x.q, x.partials, x.st, gate);
+  });
+}
+
+template <class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_rows_inv_multi(GroupMap gm, RowsMulti<S, T> m, int gate) {
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  with_nc(x.nc, [&](auto nc) {
+    k_rows_inv_body<S, T, MODE, decltype(nc)::value, SubGrid>(sg, x.g, x.dp, x.tw, x.src, x.dst, x.rpb, x.nrows,
+                                                                x.aux, x.st, gate);
+  });
+}
+
+template <class S, class T> struct ColsArgs {
+  Geo g;
+  DctPlan dp;
+  const cx<T>* tw;
+  S* data;
+  int tb;
+  const DevState* st;
+  int nc;
+};
+template <class S, class T> struct ColsMulti { ColsArgs<S, T> a[kMaxGroups]; };
+
+template <class S, class T, int DIR>
+__global__ __launch_bounds__(512) void k_cols_multi(GroupMap gm, ColsMulti<S, T> m, int gate) {
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  with_nc(x.nc, [&](auto nc) {
+    k_cols_body<S, T, DIR, decltype(nc)::value, SubGrid>(sg, x.g, x.dp, x.tw, x.data, x.tb, x.st, gate);
+  });
+}
+
+template <class S> struct ThomasArgs {
+  Geo g;
+  RefMedium rm;
+  S* t;
+  int Puse;
+  double* partials;
+  const DevState* st;
+  int ntx, ntiles;
+  int variant;  // partition rows (2, 3, 4, 5, 8, 16) + 100 when every partition has them exactly
+};
+template <class S> struct ThomasMulti { ThomasArgs<S> a[kMaxGroups]; };
+
+// Partition lengths of the multi-group tridiagonal kernel: exact 2, 3, 4,
+// 5, 8, 16 and guarded 4, 8, 16 (load axes up to 512).
+__host__ __device__ constexpr int thomas_variant(int maxm, bool exact) { return maxm + (exact ? 100 : 0); }
+
+template <class S, int TB, int P>
+__global__ __launch_bounds__(TB* P, 4) void k_thomas_multi(GroupMap gm, ThomasMulti<S> m, int gate) {
+  __shared__ double sh[6][P][TB];
+  __shared__ double red[16];
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  auto run = [&](auto mm, auto ex) {
+    constexpr int MAXM = decltype(mm)::value;
+    constexpr bool EXACT = decltype(ex)::value;
+    k_thomas_body<S, TB, P, MAXM, EXACT, ((EXACT && sizeof(S) == 4) || MAXM <= 8), SubGrid>(
+        sg, x.g, x.rm, x.t, x.Puse, x.partials, x.st, gate, x.ntx, x.ntiles, sh, red);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  switch (x.variant) {
+    case thomas_variant(16, true): run(std::integral_constant<int, 16>{}, T_{}); break;
+    case thomas_variant(8, true): run(std::integral_constant<int, 8>{}, T_{}); break;
+    case thomas_variant(5, true): run(std::integral_constant<int, 5>{}, T_{}); break;
+    case thomas_variant(4, true): run(std::integral_constant<int, 4>{}, T_{}); break;
+    case thomas_variant(3, true): run(std::integral_constant<int, 3>{}, T_{}); break;
+    case thomas_variant(2, true): run(std::integral_constant<int, 2>{}, T_{}); break;
+    case thomas_variant(4, false): run(std::integral_constant<int, 4>{}, F_{}); break;
+    case thomas_variant(8, false): run(std::integral_constant<int, 8>{}, F_{}); break;
+    default: run(std::integral_constant<int, 16>{}, F_{}); break;
+  }
+}
+
+struct FinArgs {
+  const double* partials;
+  int n;
+  int64_t pstride;
+  DevState* st;
+  double* hist;
+  int hstride;
+};
+struct FinMulti { FinArgs a[kMaxGroups]; };
+
+// one block per instance of the ensemble (group grids (instances, 1, 1))
+__global__ __launch_bounds__(1024) void k_fin_multi(GroupMap gm, FinMulti m, int op) {
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  k_fin_body<SubGrid>(sg, op, x.partials, x.n, x.pstride, x.st, x.hist, x.hstride);
+}
+
+struct FlushArgs {
+  Geo g;
+  double* p;
+  float* dlt;
+  const float* w;
+  const DevState* st;
+};
+struct FlushMulti { FlushArgs a[kMaxGroups]; };
+
+__global__ __launch_bounds__(256) void k_flush_multi(GroupMap gm, FlushMulti m) {
+  SubGrid sg;
+  const auto& x = m.a[gm.find(sg)];
+  k_flush_body<SubGrid>(sg, x.g, x.p, x.dlt, x.w, x.st);
 }
 
 }  // namespace etc

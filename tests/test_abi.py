@@ -129,3 +129,21 @@ def test_static_entry_rejects_before_touching_the_device():
     assert _static_call((1, 16, 16)) == -1
     # the largest float64 cube the array holds
     assert etc.etc_workspace_size((96, 96, 96), "float64", 0) <= etc.STATIC_SCRATCH_BYTES
+
+
+def test_ensemble_sizing_and_limits():
+    shapes = [(48, 48, 48), (64, 64, 64), (48, 48, 48)]
+    total = etc.etc_workspace_size_ensemble(shapes, "float32", 0, precision="mixed")
+    per = etc.etc_workspace_size((48, 48, 48), "float32", 0, precision="mixed")
+    # one batch workspace per shape (a batch shares its tables, so slightly under the sum of singles)
+    assert 0.99 * (2 * per + etc.etc_workspace_size((64, 64, 64), "float32", 0, precision="mixed")) <= total
+    # at most 8 distinct shapes, load axes up to 512, each shape valid
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_workspace_size_ensemble([(8 + i, 8, 8) for i in range(9)], "float64", 0)
+    assert e.value.status == -6
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_workspace_size_ensemble([(600, 8, 8)], "float64", 0)
+    assert e.value.status == -6
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_workspace_size_ensemble([(1, 8, 8)], "float64", 0)
+    assert e.value.status == -1

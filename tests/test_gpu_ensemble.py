@@ -1,0 +1,97 @@
+"""Mixed-size ensembles in one plan (etc_setup_ensemble): every kernel of a
+PCG pass is one launch for all RVEs, whatever their sizes (Section "Remarks
+on implementations": the transforms and tridiagonal systems of many problems
+are batched), each RVE with its own exit test.
+
+* against the oracle: K_eff and dK/dkappa of every RVE (float64, rtol 1e-11);
+* against the per-shape batch plans: the same pass counts and K_eff (the
+  multi-group launches run the bodies the batch plans run);
+* graph replay of the ensemble's passes equals the eager launches bit for
+  bit;
+* RVEs that converge at different passes stop independently.
+The 48^3-160^3 ensemble of the benchmark is compared with the oracle's
+stored K_eff in test_gpu_oracle_keff.py.
+"""
+
+import numpy as np
+import pytest
+
+import rvegen
+from oracle import etc_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+etc = pytest.importorskip("paper_2404_02433_amd")
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda:0")
+
+
+def grf(edges, dtype=np.float64, seed0=600):
+    return [rvegen.grf_lognormal(n, 1.0 + 0.2 * i, 4.0, seed0 + i, dtype=dtype) for i, n in enumerate(edges)]
+
+
+def test_one_launch_ensemble_matches_oracle_with_gradients():
+    edges = [12, 16, 12, 20, 16, 12]
+    kaps = grf(edges)
+    print(f"ensemble edges {edges}", flush=True)
+    out = etc.solve_ensemble([dev(k) for k in kaps], 1, rtol=1e-11, want_grad=True)
+    assert out["plans"] == 1
+    for i, k in enumerate(kaps):
+        ref = O.solve(k, 1, rtol=1e-13)
+        print(f"rve {i} ({k.shape[0]}^3): K={out['keff'][i]:.13g} oracle {ref['keff']:.13g} iters {out['iters'][i]}",
+              flush=True)
+        assert out["status"][i] == "ok"
+        assert abs(out["keff"][i] - ref["keff"]) <= 1e-9 * ref["keff"], i
+        gref = O.decanonical(O.keff_gradient(ref["problem"], ref["pcg"].p), 1)
+        g = out["grad"][i].cpu().numpy()
+        assert g.shape == k.shape
+        assert np.abs(g - gref).max() <= 1e-7 * np.abs(gref).max(), i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_launch_ensemble_equals_batch_plans(precision):
+    edges = [24, 32, 24, 40, 32, 24, 48]
+    dtype = np.float32 if precision == "mixed" else np.float64
+    kaps = [dev(k) for k in grf(edges, dtype, seed0=700)]
+    rtol = 1e-9 if precision == "fp64" else 1e-6
+    one = etc.solve_ensemble(kaps, 0, precision=precision, rtol=rtol)
+    per = etc.solve_ensemble(kaps, 0, precision=precision, rtol=rtol, mode="plans", concurrent=False)
+    print(f"{precision}: launch iters {one['iters']} plans iters {per['iters']}", flush=True)
+    assert one["status"] == per["status"] == ["ok"] * len(edges)
+    assert len(set(one["iters"])) > 1
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    for i in range(len(edges)):
+        assert abs(one["iters"][i] - per["iters"][i]) <= 1, i
+        assert abs(one["keff"][i] - per["keff"][i]) <= tol * per["keff"][i], i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_launch_ensemble_graph_equals_eager(precision):
+    edges = [20, 28, 20, 36]
+    dtype = np.float32 if precision == "mixed" else np.float64
+    kaps = [dev(k) for k in grf(edges, dtype, seed0=800)]
+    eager = etc.solve_ensemble(kaps, 2, precision=precision, rtol=1e-8 if precision == "fp64" else 1e-6)
+    graph = etc.solve_ensemble(kaps, 2, precision=precision, rtol=1e-8 if precision == "fp64" else 1e-6,
+                               use_graph=True)
+    assert graph["iters"] == eager["iters"]
+    assert graph["keff"] == eager["keff"]
+
+
+def test_one_launch_ensemble_solution_layout_and_single_solves():
+    """Solutions come back RVE after RVE in input order; each equals the
+    RVE's own single solve (float64, rtol 1e-12)."""
+    edges = [(10, 14, 12), (16, 16, 16), (10, 14, 12)]
+    rng = np.random.default_rng(5)
+    kaps = [np.exp(0.7 * rng.standard_normal(e)) for e in edges]
+    plan = etc.etc_setup_ensemble([dev(k) for k in kaps], 2, rtol=1e-12)
+    etc.etc_solve(plan)
+    flat = etc.etc_get_solution(plan)
+    parts = [t.cpu().numpy() for t in etc._split_flat(flat, plan.ensemble_shapes)]
+    plan.close()
+    for k, p in zip(kaps, parts):
+        ref = O.solve(k, 2, rtol=1e-13)
+        assert p.shape == k.shape
+        assert np.abs(p - O.decanonical(ref["pcg"].p, 2)).max() < 1e-9

@@ -520,14 +520,14 @@ def test_graph_batch_with_persistent_column_kernels(precision):
 # --------------------------------------------------------------- ensembles
 @pytest.mark.parametrize("concurrent", [True, False])
 def test_ensemble_of_mixed_sizes_matches_oracle(concurrent):
-    """solve_ensemble buckets RVEs by shape into batch plans (split when a
-    bucket exceeds the voxel cap), runs the plans one after another or at the
-    same time on streams of their own, and returns results in input order;
-    each K_eff equals the oracle's, gradients included."""
+    """solve_ensemble(mode="plans") buckets RVEs by shape into batch plans
+    (split when a bucket exceeds the voxel cap), runs the plans one after
+    another or at the same time on streams of their own, and returns results
+    in input order; each K_eff equals the oracle's, gradients included."""
     edges = [12, 16, 12, 20, 16, 12]
     kaps_np = [rvegen.grf_lognormal(n, 1.0 + 0.2 * i, 4.0, 600 + i, dtype=np.float64) for i, n in enumerate(edges)]
     out = etc.solve_ensemble([dev(k) for k in kaps_np], 1, max_batch_voxels=2 * 12 ** 3, rtol=1e-11,
-                             want_grad=True, concurrent=concurrent)
+                             want_grad=True, concurrent=concurrent, mode="plans")
     # cap of two 12^3 RVEs: 12^3 x3 -> 2 plans, 16^3 x2 -> 2 plans, 20^3 -> 1 plan
     assert out["plans"] == 5
     for i, k in enumerate(kaps_np):
