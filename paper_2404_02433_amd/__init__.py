@@ -467,12 +467,49 @@ def _split_flat(flat, shapes):
     return out
 
 
+def _split_even(kappas, parts):
+    """Indices of `parts` subsets of the RVEs with about equal voxel counts
+    (largest first, each to the lightest subset so far)."""
+    order = sorted(range(len(kappas)), key=lambda i: -kappas[i].numel())
+    bins = [[] for _ in range(parts)]
+    load = [0] * parts
+    for i in order:
+        b = load.index(min(load))
+        bins[b].append(i)
+        load[b] += kappas[i].numel()
+    return [sorted(b) for b in bins if b]
+
+
+def _run_concurrent(torch, parts, run, device):
+    """run(part) for every part, each on a stream of its own (default
+    priority) driven by a host thread; the caller's stream waits for all."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    main = torch.cuda.current_stream(device)
+    streams = [torch.cuda.Stream(device) for _ in parts]
+    for st in streams:
+        st.wait_stream(main)  # the inputs were written on the caller's stream
+
+    def on_stream(part, stream):
+        with torch.cuda.stream(stream):
+            return run(part)
+
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        results = list(ex.map(on_stream, parts, streams))
+    for st in streams:
+        main.wait_stream(st)
+    return results, streams
+
+
 def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_grad: bool = False,
-                   concurrent: bool = True, mode: str = "launch", **kw) -> dict:
+                   concurrent: bool = True, mode: str = "launch", streams: int = 1, **kw) -> dict:
     """K_eff of an ensemble of RVEs of mixed sizes, results in input order.
 
-    mode "launch" (default): one ensemble plan (etc_setup_ensemble); every
-    kernel of a pass is one launch for all RVEs, each with its own exit test.
+    mode "launch" (default): ensemble plans (etc_setup_ensemble) in which
+    every kernel of a pass is one launch for all their RVEs, each RVE with its
+    own exit test.  ``streams`` > 1 splits the RVEs into that many plans of
+    about equal voxel counts, run at the same time on streams of their own
+    (the kernels of one plan then overlap those of the others).
     mode "plans": RVEs of one shape are stacked into batch plans (at most
     ``max_batch_voxels`` voxels per plan); with ``concurrent`` the plans run at
     the same time, each on a stream of its own driven by a host thread.
@@ -480,14 +517,36 @@ def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_
     per RVE)."""
     torch = _torch()
     if mode == "launch":
-        plan = etc_setup_ensemble(kappas, axis, want_grad=want_grad, **kw)
-        etc_solve(plan)
-        out = etc_batch_results(plan)
-        out.update(etc_keff_batch(plan))
-        out["plans"] = 1
+        def run_launch(part):
+            plan = etc_setup_ensemble([kappas[i] for i in part], axis, want_grad=want_grad, **kw)
+            etc_solve(plan)
+            res = etc_batch_results(plan)
+            res.update(etc_keff_batch(plan))
+            res["grad"] = _split_flat(etc_grad(plan), plan.ensemble_shapes) if want_grad else None
+            plan.close()
+            return res
+
+        n = len(kappas)
+        parts = _split_even(kappas, max(1, min(int(streams), n)))
+        if len(parts) > 1:
+            results, sts = _run_concurrent(torch, parts, run_launch, kappas[0].device)
+            if want_grad:
+                main = torch.cuda.current_stream(kappas[0].device)
+                for res in results:
+                    for g in res["grad"]:
+                        g.record_stream(main)
+        else:
+            results = [run_launch(parts[0])]
+        out = {"keff": [None] * n, "k_in": [None] * n, "iters": [None] * n, "status": [None] * n,
+               "relres": [None] * n, "plans": len(parts)}
         if want_grad:
-            out["grad"] = _split_flat(etc_grad(plan), plan.ensemble_shapes)
-        plan.close()
+            out["grad"] = [None] * n
+        for part, res in zip(parts, results):
+            for j, i in enumerate(part):
+                for key in ("keff", "k_in", "iters", "status", "relres"):
+                    out[key][i] = res[key][j]
+                if want_grad:
+                    out["grad"][i] = res["grad"][j]
         return out
     if mode != "plans":
         raise ValueError("mode must be 'launch' or 'plans'")
@@ -509,7 +568,7 @@ def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_
     parts.sort(key=lambda part: -len(part) * kappas[part[0]].numel())
     device = kappas[0].device if n else None
 
-    def run(part, stream):
+    def run(part):
         batch = torch.stack([kappas[i] for i in part])
         plan = etc_setup_batch(batch, axis, want_grad=want_grad, **kw)
         del batch
@@ -520,26 +579,14 @@ def solve_ensemble(kappas, axis: int = 0, max_batch_voxels: int = 1 << 28, want_
         plan.close()
         return res
 
-    def on_stream(part, stream):
-        with torch.cuda.stream(stream):
-            return run(part, stream)
-
     if concurrent and len(parts) > 1:
-        from concurrent.futures import ThreadPoolExecutor
-
-        main = torch.cuda.current_stream(device)
-        streams = [torch.cuda.Stream(device) for _ in parts]  # default priority
-        for st in streams:
-            st.wait_stream(main)  # the inputs were written on the caller's stream
-        with ThreadPoolExecutor(max_workers=len(parts)) as ex:
-            results = list(ex.map(on_stream, parts, streams))
-        for st in streams:
-            main.wait_stream(st)
+        results, _ = _run_concurrent(torch, parts, run, device)
         if want_grad:
-            for res, st in zip(results, streams):
+            main = torch.cuda.current_stream(device)
+            for res in results:
                 res["grad"].record_stream(main)
     else:
-        results = [run(part, None) for part in parts]
+        results = [run(part) for part in parts]
     for part, res in zip(parts, results):
         out["plans"] += 1
         for j, i in enumerate(part):
