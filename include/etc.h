@@ -92,12 +92,23 @@ typedef struct {
   int want_grad;         /* 1: reserve the adjoint state for etc_grad (8 bytes per voxel) */
   etc_precond precond;   /* default ETC_PC_DCT */
   int autotune;          /* 1: etc_setup times the stencil's plane chunk and the
-                            tridiagonal kernel's grid on the plan's own buffers and
-                            keeps the fastest (cached per problem shape); default 0 */
+                            tridiagonal kernel's block shape and grid on the plan's
+                            own buffers and keeps the fastest (cached per problem
+                            shape); default 0 */
   int use_graph;         /* 1: etc_solve captures `poll_every` passes in a HIP graph on
                             first use (per solution buffer and Dirichlet pair) and
                             replays it; ignored while a kernel timer is set.  The
                             results equal those of the eager path.  Default 0. */
+  int thomas_modes;      /* tridiagonal block shape: transverse modes per block and */
+  int thomas_parts;      /* partitions per line, both 0 (default) for the built-in
+                            choice by load-axis length; compiled shapes (float32 /
+                            float64 rows): 32x8, 16x16, 32x16 and 32x32 / 16x32, plus
+                            64x8 (float32).  32x8 holds load axes up to 128, 16x16
+                            and 32x16 up to 256, the 32-partition shapes up to 2048
+                            (512 in the mixed form);
+                            etc_setup returns ETC_E_UNSUPPORTED for a shape that is
+                            not compiled or does not hold the load axis.  With
+                            autotune the tuner keeps this shape and times its grid. */
 } etc_options;
 
 typedef struct {
@@ -143,8 +154,8 @@ etc_status etc_workspace_size(const int64_t n[3], etc_dtype dt, int axis, const 
  *   n     : user dims; each >= 1 and <= 2^20, n[axis] >= 2.  Beyond the
  *           kernels' limits ETC_E_UNSUPPORTED: load axis n[axis] <= 2048 (the
  *           tridiagonal kernel holds a line as 32 partitions of at most 64
- *           rows), first transverse axis <= 65535, transverse plane < 2^31
- *           voxels.
+ *           rows; 512, partitions of at most 16 rows, in the mixed form),
+ *           first transverse axis <= 65535, transverse plane < 2^31 voxels.
  *   bc    : p_in != p_out (eq:effective formula needs a drop).
  *   opt   : may be NULL (defaults).  If opt->workspace is NULL the plan
  *           allocates its device memory with hipMalloc and frees it in
@@ -268,8 +279,11 @@ etc_status etc_set_kernel_timer(etc_plan* plan, int kernel_id);
 etc_status etc_kernel_time(const etc_plan* plan, double* total_ms, int* launches);
 
 /* Launch shapes of a plan: the stencil's plane chunk, the tridiagonal
- * kernel's blocks per instance, and whether the autotuner chose them. */
-etc_status etc_launch_info(const etc_plan* plan, int* kchunk, int* thomas_blocks, int* tuned);
+ * kernel's persistent blocks per instance and its block shape (transverse
+ * modes times partitions of each line), and whether the autotuner chose
+ * them.  Any output pointer may be NULL. */
+etc_status etc_launch_info(const etc_plan* plan, int* kchunk, int* thomas_blocks, int* tuned, int* thomas_modes,
+                           int* thomas_parts);
 
 /* Device-to-device copy of n doubles by a plain streaming kernel (16-byte
  * accesses): calibrates hardware byte counters and measures the streaming

@@ -63,6 +63,8 @@ class _Options(ctypes.Structure):
         ("precond", ctypes.c_int),
         ("autotune", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("thomas_modes", ctypes.c_int),
+        ("thomas_parts", ctypes.c_int),
     ]
 
 
@@ -88,8 +90,7 @@ class _Result(ctypes.Structure):
 
 _SYMBOLS = {
     "etc_options_default": (None, [ctypes.POINTER(_Options)]),
-    "etc_launch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(ctypes.c_int)]),
+    "etc_launch_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
     "etc_workspace_size": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]),
     "etc_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), _BC, ctypes.c_int,
@@ -182,7 +183,7 @@ def _torch():
 
 def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=20, poll_every=8, kref="mid",
              kref_user=None, L=None, stream=None, want_grad=False, precond="dct", use_graph=False,
-             autotune=False) -> _Options:
+             autotune=False, thomas_shape=None) -> _Options:
     lib = load_library()
     o = _Options()
     lib.etc_options_default(ctypes.byref(o))
@@ -203,6 +204,8 @@ def _options(precision="fp64", rtol=1e-6, max_iter=1000, refine_every=20, poll_e
     o.precond = {"dct": 0, "none": 1}[precond]
     o.use_graph = 1 if use_graph else 0
     o.autotune = 1 if autotune else 0
+    if thomas_shape is not None:
+        o.thomas_modes, o.thomas_parts = (int(v) for v in thomas_shape)
     return o
 
 
@@ -257,7 +260,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
               rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 20, poll_every: int = 8,
               kref: str = "mid", kref_user=None, L=None, want_grad: bool = False, source=None,
               p_in_face=None, p_out_face=None, precond: str = "dct", use_graph: bool = False,
-              autotune: bool = False) -> Plan:
+              autotune: bool = False, thomas_shape=None) -> Plan:
     """Preparation phase on device data (user layout, load axis ``axis``).
 
     ``kappa`` is one tensor (isotropic) or a sequence of three tensors, the
@@ -265,7 +268,8 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
     ``source`` (float64, kappa's shape), ``p_in_face`` / ``p_out_face``
     (float64 over the two transverse axes in user order) are optional.
     ``use_graph`` replays the PCG passes from a captured HIP graph;
-    ``autotune`` times launch-shape candidates at setup and keeps the fastest."""
+    ``autotune`` times launch-shape candidates at setup and keeps the fastest;
+    ``thomas_shape`` = (modes, partitions) fixes the tridiagonal block shape."""
     torch = _torch()
     comps = list(kappa) if isinstance(kappa, (list, tuple)) else [kappa]
     if len(comps) not in (1, 3):
@@ -282,7 +286,7 @@ def etc_setup(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, preci
     dtype = "float64" if k0.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(k0.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad, precond, use_graph, autotune)
+                 want_grad, precond, use_graph, autotune, thomas_shape)
     n = _dims(k0.shape)
     pr = _Problem()
     keep = list(comps)
@@ -348,7 +352,8 @@ def etc_solve_static(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0
 def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0, precision: str = "fp64",
                     rtol: float = 1e-6, max_iter: int = 1000, refine_every: int = 20, poll_every: int = 8,
                     kref: str = "mid", kref_user=None, L=None, want_grad: bool = False,
-                    precond: str = "dct", use_graph: bool = False, autotune: bool = False) -> Plan:
+                    precond: str = "dct", use_graph: bool = False, autotune: bool = False,
+                    thomas_shape=None) -> Plan:
     """Batch of same-size RVEs: ``kappa`` has shape (B, n0, n1, n2)."""
     torch = _torch()
     if not isinstance(kappa, torch.Tensor) or kappa.device.type != "cuda" or kappa.dim() != 4:
@@ -359,7 +364,7 @@ def etc_setup_batch(kappa, axis: int = 0, p_in: float = 1.0, p_out: float = 0.0,
     dtype = "float64" if kappa.dtype == torch.float64 else "float32"
     stream = torch.cuda.current_stream(kappa.device)
     o = _options(precision, rtol, max_iter, refine_every, poll_every, kref, kref_user, L, stream.cuda_stream,
-                 want_grad, precond, use_graph, autotune)
+                 want_grad, precond, use_graph, autotune, thomas_shape)
     nb = int(kappa.shape[0])
     n = _dims(kappa.shape[1:])
     nbytes = ctypes.c_size_t(0)
@@ -718,10 +723,13 @@ def etc_kernel_time(plan: Plan):
 
 def etc_launch_info(plan: Plan) -> dict:
     """Launch shapes of a plan (stencil plane chunk, tridiagonal blocks per
-    instance) and whether the autotuner chose them."""
-    kc, tb, tu = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(load_library().etc_launch_info(plan.handle, ctypes.byref(kc), ctypes.byref(tb), ctypes.byref(tu)))
-    return {"kchunk": kc.value, "thomas_blocks": tb.value, "tuned": bool(tu.value)}
+    instance and block shape: modes x partitions) and whether the autotuner
+    chose them."""
+    kc, tb, tu, tm, tp = (ctypes.c_int() for _ in range(5))
+    _check(load_library().etc_launch_info(plan.handle, ctypes.byref(kc), ctypes.byref(tb), ctypes.byref(tu),
+                                          ctypes.byref(tm), ctypes.byref(tp)))
+    return {"kchunk": kc.value, "thomas_blocks": tb.value, "tuned": bool(tu.value),
+            "thomas_shape": (tm.value, tp.value)}
 
 
 def etc_copy_f64(src, dst):

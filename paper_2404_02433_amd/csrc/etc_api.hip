@@ -43,9 +43,7 @@ constexpr int kThreads = 256;
 constexpr int stencil_tbw(size_t elt) { return elt == 4 ? 128 : 64; }
 constexpr int kStencilTAH = 16;
 constexpr int kMaxGridStride = 2048;   // grid of the grid-stride reduction kernels
-constexpr int kThomasP = 32;           // partitions per line in the tridiagonal kernel
-constexpr int kThomasTB = 16;          // modes (lines) per tridiagonal block, float64 (128-byte rows)
-constexpr int kThomasTBf = 32;         // float32: 32 modes keep whole 128-byte rows
+constexpr int kThomasP = 32;           // most partitions per line in the tridiagonal kernel
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -73,7 +71,10 @@ struct LaunchCfg {
   int colsPers;  // blocks of the persistent column kernels (0: one block per tile)
   // tridiagonal
   dim3 gridThomas;  // persistent blocks per instance (x) times instances (z)
+  int tvar;         // variant (ThomasVariants): block of thomasTB modes x thomasP partitions
+  int thomasTB, thomasP;
   int Puse, maxm, nThomas, thomasTiles;
+  int nThomasMax;  // tiles per instance of the narrowest block shape (autotuner candidates)
   // grid-stride kernels
   dim3 gridStride;
   int nStride;
@@ -238,6 +239,52 @@ void set_stencil_chunk(LaunchCfg& lc, const Geo& g, int kchunk) {
   lc.nRes = gx64 * gy * nch;
 }
 
+// Variant of the tridiagonal kernel for blocks of tb modes x p partitions
+// on a load axis of nL rows: the exact one when every partition has the same
+// rows, else the smallest bound that holds them; -1 when none is compiled.
+template <class S> int thomas_pick(int tb, int p, int nL) {
+  const int Puse = std::max(1, std::min(p, nL / 2));
+  const int m = (nL + Puse - 1) / Puse;
+  int best = -1;
+  for (int i = 0; i < ThomasVariants<S>::n; ++i) {
+    const ThomasVariant& v = ThomasVariants<S>::v[i];
+    if (v.tb != tb || v.p != p) continue;
+    if (v.exact) {
+      if (Puse == p && nL == p * v.rows) return i;
+    } else if (v.rows >= m && (best < 0 || v.rows < ThomasVariants<S>::v[best].rows)) {
+      best = i;
+    }
+  }
+  return best;
+}
+
+// Block shape of the tridiagonal kernel by load-axis length, from timings of
+// every compiled shape on batches of cubes (the autotuner may pick another):
+// 32 x 8 up to 128 rows, 16 x 16 up to 192, 32 x 16 up to 256, then 32
+// partitions of 32 (float32) or 16 (float64) modes.
+void thomas_default_shape(int nL, size_t elt, int& tb, int& p) {
+  if (nL <= 128) tb = 32, p = 8;
+  else if (nL <= 192) tb = 16, p = 16;
+  else if (nL <= 256) tb = 32, p = 16;
+  else tb = elt == 4 ? 32 : 16, p = kThomasP;
+}
+
+// Launch shape of the tridiagonal kernel for tb x p blocks; false when no
+// variant of that shape holds this load axis.
+bool set_thomas(LaunchCfg& lc, const Geo& g, size_t elt, int tb, int p) {
+  const int v = elt == 4 ? thomas_pick<float>(tb, p, g.nL) : thomas_pick<double>(tb, p, g.nL);
+  if (v < 0) return false;
+  lc.tvar = v;
+  lc.thomasTB = tb;
+  lc.thomasP = p;
+  lc.Puse = std::max(1, std::min(p, g.nL / 2));
+  lc.maxm = (g.nL + lc.Puse - 1) / lc.Puse;
+  lc.thomasTiles = (g.nb + tb - 1) / tb;
+  lc.nThomas = lc.thomasTiles * g.na;                // tiles (and partial sums) per instance
+  lc.gridThomas = dim3(lc.nThomas, 1, g.nseg);       // capped to the resident blocks at setup
+  return true;
+}
+
 LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size_t elt, bool ortho) {
   LaunchCfg lc{};
   const size_t cx_sz = 2 * elt;
@@ -285,14 +332,11 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   }
   // tridiagonal
   {
-    int Puse = std::max(1, std::min(kThomasP, g.nL / 2));
-    int m = (g.nL + Puse - 1) / Puse;
-    lc.Puse = Puse;
-    lc.maxm = m;
-    const int tbm = elt == 4 ? kThomasTBf : kThomasTB;
-    lc.thomasTiles = (g.nb + tbm - 1) / tbm;
-    lc.nThomas = lc.thomasTiles * g.na;  // tiles (and partial sums) per instance
-    lc.gridThomas = dim3(lc.nThomas, 1, ns);  // capped to the resident blocks at setup
+    int tb = 0, p = 0;
+    thomas_default_shape(g.nL, elt, tb, p);
+    lc.tvar = -1;  // stays -1 when no compiled variant holds the load axis (setup refuses the plan)
+    if (!set_thomas(lc, g, elt, tb, p)) (void)set_thomas(lc, g, elt, elt == 4 ? 32 : 16, kThomasP);
+    lc.nThomasMax = ((g.nb + 15) / 16) * g.na;  // no compiled shape has fewer than 16 modes
   }
   int64_t gs = (g.V + kThreads - 1) / kThreads;
   lc.nStride = (int)std::min<int64_t>(gs, std::max<int64_t>(8, kMaxGridStride / ns));
@@ -311,6 +355,7 @@ int max_partials_of(const LaunchCfg& lc) {
   m = std::max<int64_t>(m, lc.nR);
   m = std::max<int64_t>(m, lc.nRows);
   m = std::max<int64_t>(m, lc.nThomas);
+  m = std::max<int64_t>(m, lc.nThomasMax);
   m = std::max<int64_t>(m, (int64_t)lc.nStride * 12);
   m = std::max<int64_t>(m, (int64_t)lc.nKeff * 2);
   return (int)m;
@@ -329,6 +374,8 @@ etc_status validate(const int64_t n[3], int axis, const etc_options& o) {
   if ((int64_t)na * nb > (int64_t)1 << 31) return fail(ETC_E_UNSUPPORTED, "transverse plane too large");
   if (na > 65535) return fail(ETC_E_UNSUPPORTED, "transverse axis a longer than 65535");
   if (nL > kThomasP * 64) return fail(ETC_E_UNSUPPORTED, "load axis longer than 2048");
+  if (o.precision == ETC_MIXED && nL > kThomasP * 16)
+    return fail(ETC_E_UNSUPPORTED, "mixed form: load axis longer than 512");
   if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(ETC_E_INVALID, "rtol must be > 0");
   if (o.max_iter < 0) return fail(ETC_E_INVALID, "max_iter must be >= 0");
   if (o.precision != ETC_FP64 && o.precision != ETC_MIXED) return fail(ETC_E_INVALID, "bad precision");
@@ -593,32 +640,22 @@ template <class S> struct Ops {
     return rm;
   }
 
-  // Tridiagonal kernel of this plan's shape: exact partitions (nL = 32 m)
-  // for the common lengths, else the guarded variant with room for m rows.
+  // Tridiagonal kernel of this plan's variant (block shape and partition rows).
   template <class F>
-  static void with_thomas(const LaunchCfg& lc, int nL, F&& f) {
-    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
-    constexpr int PP = kThomasP;
-    const bool exact = lc.Puse == PP && nL == PP * lc.maxm;
-    if (exact && lc.maxm == 16) f(&k_thomas<S, TB, PP, 16, true>);
-    else if (exact && lc.maxm == 8) f(&k_thomas<S, TB, PP, 8, true>);
-    else if (exact && lc.maxm == 5) f(&k_thomas<S, TB, PP, 5, true>);
-    else if (exact && lc.maxm == 4) f(&k_thomas<S, TB, PP, 4, true>);
-    else if (exact && lc.maxm == 3) f(&k_thomas<S, TB, PP, 3, true>);
-    else if (exact && lc.maxm == 2) f(&k_thomas<S, TB, PP, 2, true>);
-    else if (lc.maxm <= 4) f(&k_thomas<S, TB, PP, 4, false>);
-    else if (lc.maxm <= 8) f(&k_thomas<S, TB, PP, 8, false>);
-    else if (lc.maxm <= 16) f(&k_thomas<S, TB, PP, 16, false>);
-    else if (lc.maxm <= 32) f(&k_thomas<S, TB, PP, 32, false>);
-    else f(&k_thomas<S, TB, PP, 64, false>);
+  static void with_thomas(const LaunchCfg& lc, F&& f) {
+    with_thomas_variant<S>(lc.tvar, [&](auto ic) {
+      constexpr ThomasVariant v = ThomasVariants<S>::v[decltype(ic)::value];
+      f(&k_thomas<S, v.tb, v.p, v.rows, v.exact>);
+    });
   }
 
   // Setup-time autotuner: time the stencil for plane chunks of 8 .. nL and
-  // the tridiagonal kernel for persistent grids of 1x and 2x the resident
-  // blocks and for one block per tile, on this plan's own buffers, and keep
-  // the fastest of each (cached per problem shape for the process).
+  // the tridiagonal kernel for every compiled block shape that holds the load
+  // axis, each with persistent grids of 1x and 2x the resident blocks and
+  // one block per tile, on this plan's own buffers, and keep the fastest of
+  // each (cached per problem shape for the process).
   struct Tuned {
-    int kchunk, thomas_x;
+    int kchunk, thomas_tb, thomas_p, thomas_x;
   };
   static etc_status autotune(etc_plan* P) {
     // shared by every plan of the process (plans may be set up from several threads)
@@ -629,12 +666,14 @@ template <class S> struct Ops {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     const std::vector<int64_t> key = {dev, g.nL, g.na, g.nb, P->nseg, (int64_t)sizeof(S), P->ortho ? 1 : 0,
-                                      (int64_t)lc.gridThomas.x};
+                                      P->opt.thomas_modes, P->opt.thomas_parts};
     {
       std::lock_guard<std::mutex> lock(mu);
       for (auto& e : cache)
         if (e.first == key) {
           set_stencil_chunk(lc, g, e.second.kchunk);
+          if (!set_thomas(lc, g, sizeof(S), e.second.thomas_tb, e.second.thomas_p))
+            return fail(ETC_E_UNSUPPORTED, "autotune: cached tridiagonal shape no longer valid");
           lc.gridThomas.x = e.second.thomas_x;
           P->tuned = 1;
           return ETC_OK;
@@ -657,7 +696,7 @@ template <class S> struct Ops {
     if (hipMemsetAsync(P->w, 0, vb, P->stream) != hipSuccess || hipMemsetAsync(P->t, 0, vb, P->stream) != hipSuccess)
       s = fail(ETC_E_HIP, "autotune: memset failed");
     // stencil chunk
-    Tuned best{lc.kchunk, (int)lc.gridThomas.x};
+    Tuned best{lc.kchunk, lc.thomasTB, lc.thomasP, (int)lc.gridThomas.x};
     if (!s) {
       float tbest = 1e30f;
       for (int kc = std::min(8, g.nL);; kc *= 2) {
@@ -674,19 +713,33 @@ template <class S> struct Ops {
       }
       set_stencil_chunk(lc, g, best.kchunk);
     }
-    // tridiagonal grid
+    // tridiagonal block shape and grid
     if (!s) {
-      const int resident = (int)lc.gridThomas.x;
       float tbest = 1e30f;
-      const int cands[3] = {resident, std::min(lc.nThomas, 2 * resident), lc.nThomas};
-      for (int c : cands) {
-        lc.gridThomas.x = c;
-        const float ms = time_it([&] { (void)thomas(P, (S*)P->t, nullptr, nullptr, 0); });
-        if (ms < tbest) {
-          tbest = ms;
-          best.thomas_x = c;
+      std::vector<std::pair<int, int>> shapes;
+      for (const ThomasVariant& v : ThomasVariants<S>::v)
+        if (std::find(shapes.begin(), shapes.end(), std::make_pair(v.tb, v.p)) == shapes.end())
+          shapes.push_back({v.tb, v.p});
+      const bool fixed = P->opt.thomas_modes || P->opt.thomas_parts;
+      for (const auto& sh : shapes) {
+        if (fixed && sh != std::make_pair(P->opt.thomas_modes, P->opt.thomas_parts)) continue;
+        if (!set_thomas(lc, g, sizeof(S), sh.first, sh.second)) continue;
+        if ((s = thomas_grid(P))) break;
+        const int resident = (int)lc.gridThomas.x;
+        const int cands[3] = {resident, std::min(lc.nThomas, 2 * resident), lc.nThomas};
+        for (int c : cands) {
+          lc.gridThomas.x = c;
+          const float ms = time_it([&] { (void)thomas(P, (S*)P->t, nullptr, nullptr, 0); });
+          if (ms < tbest) {
+            tbest = ms;
+            best.thomas_tb = sh.first;
+            best.thomas_p = sh.second;
+            best.thomas_x = c;
+          }
         }
       }
+      if (!set_thomas(lc, g, sizeof(S), best.thomas_tb, best.thomas_p) && !s)
+        s = fail(ETC_E_UNSUPPORTED, "autotune: no tridiagonal shape");
       lc.gridThomas.x = best.thomas_x;
     }
     (void)hipEventDestroy(e0);
@@ -732,13 +785,12 @@ template <class S> struct Ops {
   // Persistent grid of the tridiagonal kernel: the blocks that fit on the device at once.
   static etc_status thomas_grid(etc_plan* P) {
     LaunchCfg& lc = P->lc;
-    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
     int dev = 0, cus = 0, occ = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     hipError_t e = hipSuccess;
-    with_thomas(lc, P->g.nL, [&](auto fn) {
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, TB * kThomasP, 0);
+    with_thomas(lc, [&](auto fn) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, lc.thomasTB * lc.thomasP, 0);
     });
     if (e != hipSuccess) return fail(ETC_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
     const int ns = P->nseg;
@@ -751,9 +803,9 @@ template <class S> struct Ops {
   static etc_status thomas(etc_plan* P, S* t, double* partials, const DevState* st, int gate) {
     const LaunchCfg& lc = P->lc;
     const RefMedium rm = ref(P);
-    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
-    const int threads = TB * kThomasP;
-    with_thomas(lc, P->g.nL, [&](auto fn) {
+    const int threads = lc.thomasTB * lc.thomasP;
+    if (lc.tvar < 0 || lc.tvar >= ThomasVariants<S>::n) return fail(ETC_E_UNSUPPORTED, "no tridiagonal variant");
+    with_thomas(lc, [&](auto fn) {
       fn<<<lc.gridThomas, threads, 0, P->stream>>>(P->g, rm, t, lc.Puse, partials, st, gate, lc.thomasTiles,
                                                    lc.nThomas);
     });
@@ -1150,25 +1202,37 @@ template <class S> struct Ops {
     return ETC_OK;
   }
 
+  // One launch per tridiagonal variant among the groups (each group runs the
+  // variant its own plan launches).
   static etc_status thomas_multi(etc_plan* E) {
-    constexpr int TB = sizeof(S) == 4 ? kThomasTBf : kThomasTB;
-    GroupMap gm{};
-    ThomasMulti<S> m{};
-    unsigned tot = 0;
-    for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
-      etc_plan* P = E->groups[gi];
-      const LaunchCfg& lc = P->lc;
-      add_group(gm, gi, dim3(E->multi_thomas_per[gi], 1, P->nseg), tot);
-      // the variant the group's own plan launches (with_thomas)
-      int maxm = lc.maxm;
-      const bool exact = lc.Puse == kThomasP && P->g.nL == kThomasP * maxm &&
-                         (maxm == 16 || maxm == 8 || maxm == 5 || maxm == 4 || maxm == 3 || maxm == 2);
-      if (!exact) maxm = maxm <= 4 ? 4 : (maxm <= 8 ? 8 : 16);
-      m.a[gi] = ThomasArgs<S>{P->g, ref(P), (S*)P->t, lc.Puse, P->partials, P->st, lc.thomasTiles, lc.nThomas,
-                              thomas_variant(maxm, exact)};
+    std::vector<int> vars;
+    for (const etc_plan* P : E->groups)
+      if (std::find(vars.begin(), vars.end(), P->lc.tvar) == vars.end()) vars.push_back(P->lc.tvar);
+    for (int var : vars) {
+      GroupMap gm{};
+      ThomasMulti<S> m{};
+      unsigned tot = 0;
+      int j = 0;
+      for (int gi = 0; gi < (int)E->groups.size(); ++gi) {
+        etc_plan* P = E->groups[gi];
+        const LaunchCfg& lc = P->lc;
+        if (lc.tvar != var) continue;
+        add_group(gm, j, dim3(E->multi_thomas_per[gi], 1, P->nseg), tot);
+        m.a[j++] = ThomasArgs<S>{P->g, ref(P), (S*)P->t, lc.Puse, P->partials, P->st, lc.thomasTiles, lc.nThomas,
+                                 var};
+      }
+      bool launched = false;
+      with_thomas_variant<S>(var, [&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        // ensemble load axes stop at 512: partitions of at most 16 rows
+        if constexpr (ThomasVariants<S>::v[I].rows <= 16) {
+          k_thomas_multi<S, I><<<tot, ThomasVariants<S>::v[I].threads(), 0, E->stream>>>(gm, m, 1);
+          launched = true;
+        }
+      });
+      if (!launched) return fail(ETC_E_UNSUPPORTED, "ensemble: no tridiagonal variant");
+      LAUNCHCHK("thomas_multi");
     }
-    k_thomas_multi<S, TB, kThomasP><<<tot, TB * kThomasP, 0, E->stream>>>(gm, m, 1);
-    LAUNCHCHK("thomas_multi");
     return ETC_OK;
   }
 
@@ -1239,14 +1303,19 @@ void etc_options_default(etc_options* o) {
   o->precond = ETC_PC_DCT;
   o->use_graph = 0;
   o->autotune = 0;
+  o->thomas_modes = 0;
+  o->thomas_parts = 0;
 }
 
-etc_status etc_launch_info(const etc_plan* P, int* kchunk, int* thomas_blocks, int* tuned) {
+etc_status etc_launch_info(const etc_plan* P, int* kchunk, int* thomas_blocks, int* tuned, int* thomas_modes,
+                           int* thomas_parts) {
   if (P && !P->groups.empty()) return fail(ETC_E_INVALID, "not defined for an ensemble plan (use the batch calls)");
   if (!P) return fail(ETC_E_INVALID, "plan is NULL");
   if (kchunk) *kchunk = P->lc.kchunk;
   if (thomas_blocks) *thomas_blocks = (int)P->lc.gridThomas.x;
   if (tuned) *tuned = P->tuned;
+  if (thomas_modes) *thomas_modes = P->lc.thomasTB;
+  if (thomas_parts) *thomas_parts = P->lc.thomasP;
   return ETC_OK;
 }
 
@@ -1355,6 +1424,11 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
   P->dpa = make_dct_plan(na);
   P->dpb = make_dct_plan(nb);
   P->lc = make_launch(g, P->dpa, P->dpb, es, ps.ortho);
+  if (((o.thomas_modes || o.thomas_parts) && !set_thomas(P->lc, g, es, o.thomas_modes, o.thomas_parts)) ||
+      P->lc.tvar < 0) {
+    delete P;
+    return fail(ETC_E_UNSUPPORTED, "no compiled tridiagonal block of that shape holds this load axis");
+  }
   if (P->lc.gridCols.y > 65535 || P->lc.gridA.z > 65535) {
     delete P;
     return fail(ETC_E_UNSUPPORTED, "batch too large: load planes times instances exceeds 65535");

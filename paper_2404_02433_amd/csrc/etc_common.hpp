@@ -55,6 +55,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Orders the shared-memory accesses of one wave: accesses before it complete
+// (and are visible to the wave's other lanes) before any after it.  Lanes
+// that exchange data through shared memory within one wave need this, not a
+// block barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Deterministic block sum: fixed shuffle tree per wave, then the wave sums in
 // order.  Result valid in thread 0.  `lds` holds >= 16 doubles.
 __device__ __forceinline__ double block_sum(double v, double* lds) {

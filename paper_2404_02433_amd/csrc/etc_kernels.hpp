@@ -1419,9 +1419,10 @@ __device__ __forceinline__ double neumann_lambda(int k, double step) {
 // thread moves its two separator couplings to the right-hand side and
 // re-solves its block with the stored pivots.
 //
-// Also returns the partial of r . z: by the DCT's Parseval relation it equals
-// (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the transformed r;
-// per block, t . z = t^T M^{-1} t + (coupling) * (ends of M^{-1} t).
+// Also returns the partial of r . z per tile: by the DCT's Parseval relation
+// it equals (4 / (na nb)) sum alpha_a' alpha_b' t . z over modes, t the
+// transformed r; per partition, t . z = t^T M^{-1} t + (coupling) * (ends of
+// M^{-1} t).
 //
 // The mode's shift s comes from eigenvalues computed in registers
 // (neumann_lambda), not from a table in memory.
@@ -1440,7 +1441,9 @@ __device__ __forceinline__ double neumann_lambda(int k, double step) {
 template <class S, int TB, int P, int MAXM, bool EXACT, bool PF, class BG>
 __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
-                                                  int gate, int ntx, int ntiles, double (&sh)[6][P][TB], double* red) {
+                                                  int gate, int ntx, int ntiles, double (&sh)[6][P][TB + 1],
+                                                  double* red) {
+  static_assert(64 % P == 0, "the P threads of a line must sit in one wave");
   // instance bg.bz() of a batch
   if (st) st += bg.bz();
   if (gated_out(st, gate)) return;
@@ -1466,7 +1469,6 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
   const double dlast = (pok && !right) ? (kr[4] * 2.0 - kL) : 0.0;
   const int64_t plane = g.plane;
   const int nsep = Peff - 1;
-  const int q = p;
 
   auto row_ok = [&](int j) { return EXACT ? (j < MAXM - 1 || !right) : (j < lenp); };
   auto load = [&](int tile, S* v, S& vs) {
@@ -1545,6 +1547,9 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
         }
       }
       y_last = dprev;
+      // what the separators need of this partition (stored as they are:
+      // storing the separator's partial sums instead made the compiler
+      // spill hundreds of registers in the guarded float64 variants)
       sh[0][p][l] = y_first;
       sh[1][p][l] = y_last;
       sh[2][p][l] = m11;
@@ -1556,48 +1561,100 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
     // Separator q (the last row of partition q) couples to q - 1 and q + 1:
     // L_q x_{q-1} + B_q x_q + U_q x_{q+1} = r_q.  Parallel cyclic reduction:
     // at stride h every row eliminates its neighbours q - h and q + h, so
-    // after ceil(log2 nsep) steps each row stands alone.
-    const bool sep = line_ok && q < nsep;
-    double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
-    if (sep) {
-      // the separator is an interior row (never k = 0 or nL - 1)
-      Lq = (q > 0) ? -a2 * sh[4][q][l] : 0.0;
-      Bq = Dint - a2 * (sh[3][q][l] + sh[2][q + 1][l]);
-      Uq = (q + 1 < nsep) ? -a2 * sh[4][q + 1][l] : 0.0;
-      rq = sh[5][q][l] - aoff * sh[1][q][l] - aoff * sh[0][q + 1][l];
-    }
-    for (int h = 1; h < nsep; h <<= 1) {
-      __syncthreads();  // every read of the previous contents is done
-      const double iB = frcp(Bq);
+    // after ceil(log2 nsep) steps each row stands alone.  Threads take the
+    // separators line by line (thread = line * P + separator): a line's
+    // separators sit in P adjacent lanes of one wave, which exchange rows
+    // through shared memory with wave-level ordering only, no block barrier.
+    if constexpr (MAXM <= 16) {
+      const int q = tid % P, ls = tid / P;
+      const int bs = (tile % ntx) * TB + ls;  // the separator's mode b'
+      const bool sep = bs < g.nb && q < nsep;
+      double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
       if (sep) {
-        sh[0][q][l] = Lq;
-        sh[1][q][l] = Uq;
-        sh[2][q][l] = rq;
-        sh[3][q][l] = iB;
+        // the separator is an interior row (never k = 0 or nL - 1); its
+        // line's diagonal is formed again (the thread worked another line)
+        const double Ds = Dint0 + neumann_lambda(am, rm.step_a) * ka + neumann_lambda(bs, rm.step_b) * kb;
+        Lq = (q > 0) ? -a2 * sh[4][q][ls] : 0.0;
+        Bq = Ds - a2 * (sh[3][q][ls] + sh[2][q + 1][ls]);
+        Uq = (q + 1 < nsep) ? -a2 * sh[4][q + 1][ls] : 0.0;
+        rq = sh[5][q][ls] - aoff * sh[1][q][ls] - aoff * sh[0][q + 1][ls];
+      }
+      for (int h = 1; h < nsep; h <<= 1) {
+        wave_sync();  // every lane has read the slots the writes below replace
+        // each row publishes its L, U, r scaled by its 1/B
+        const double iB = frcp(Bq);
+        if (sep) {
+          sh[0][q][ls] = Lq * iB;
+          sh[1][q][ls] = Uq * iB;
+          sh[2][q][ls] = rq * iB;
+        }
+        wave_sync();
+        if (sep) {
+          double nL_ = 0.0, nU = 0.0, nB = Bq, nr = rq;
+          if (q - h >= 0) {
+            nL_ = -Lq * sh[0][q - h][ls];
+            nB -= Lq * sh[1][q - h][ls];
+            nr -= Lq * sh[2][q - h][ls];
+          }
+          if (q + h < nsep) {
+            nU = -Uq * sh[1][q + h][ls];
+            nB -= Uq * sh[0][q + h][ls];
+            nr -= Uq * sh[2][q + h][ls];
+          }
+          Lq = nL_;
+          Uq = nU;
+          Bq = nB;
+          rq = nr;
+        }
+      }
+      // separator value x_q (slot 5 of partition q was read only by this thread)
+      if (sep) sh[5][q][ls] = rq / Bq;
+    } else {
+      // partitions longer than 16 rows (load axes beyond 512): separator q
+      // is taken by the thread of partition q, rows exchanged through
+      // shared memory with block barriers
+      const int q = p;
+      const bool sep = line_ok && q < nsep;
+      double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
+      if (sep) {
+        Lq = (q > 0) ? -a2 * sh[4][q][l] : 0.0;
+        Bq = Dint - a2 * (sh[3][q][l] + sh[2][q + 1][l]);
+        Uq = (q + 1 < nsep) ? -a2 * sh[4][q + 1][l] : 0.0;
+        rq = sh[5][q][l] - aoff * sh[1][q][l] - aoff * sh[0][q + 1][l];
+      }
+      for (int h = 1; h < nsep; h <<= 1) {
+        __syncthreads();  // every read of the previous contents is done
+        const double iB = frcp(Bq);
+        if (sep) {
+          sh[0][q][l] = Lq;
+          sh[1][q][l] = Uq;
+          sh[2][q][l] = rq;
+          sh[3][q][l] = iB;
+        }
+        __syncthreads();
+        if (sep) {
+          double nL_ = 0.0, nU = 0.0, nB = Bq, nr = rq;
+          if (q - h >= 0) {
+            const double al = -Lq * sh[3][q - h][l];
+            nL_ = al * sh[0][q - h][l];
+            nB += al * sh[1][q - h][l];
+            nr += al * sh[2][q - h][l];
+          }
+          if (q + h < nsep) {
+            const double ga = -Uq * sh[3][q + h][l];
+            nU = ga * sh[1][q + h][l];
+            nB += ga * sh[0][q + h][l];
+            nr += ga * sh[2][q + h][l];
+          }
+          Lq = nL_;
+          Uq = nU;
+          Bq = nB;
+          rq = nr;
+        }
       }
       __syncthreads();
-      if (sep) {
-        double nL_ = 0.0, nU = 0.0, nB = Bq, nr = rq;
-        if (q - h >= 0) {
-          const double al = -Lq * sh[3][q - h][l];
-          nL_ = al * sh[0][q - h][l];
-          nB += al * sh[1][q - h][l];
-          nr += al * sh[2][q - h][l];
-        }
-        if (q + h < nsep) {
-          const double ga = -Uq * sh[3][q + h][l];
-          nU = ga * sh[1][q + h][l];
-          nB += ga * sh[0][q + h][l];
-          nr += ga * sh[2][q + h][l];
-        }
-        Lq = nL_;
-        Uq = nU;
-        Bq = nB;
-        rq = nr;
-      }
+      if (sep) sh[5][q][l] = rq / Bq;
     }
-    __syncthreads();
-    if (sep) sh[5][q][l] = rq / Bq;  // separator value x_q
     __syncthreads();
     double acc = 0.0, zr = 0.0;
     if (active) {
@@ -1669,9 +1726,65 @@ template <class S, int TB, int P, int MAXM, bool EXACT, bool PF = ((EXACT && siz
 __global__ __launch_bounds__(TB* P, 4) void k_thomas(Geo g, RefMedium rm, S* __restrict__ t, int Puse,
                                                   double* __restrict__ partials, const DevState* __restrict__ st,
                                                   int gate, int ntx, int ntiles) {
-  __shared__ double sh[6][P][TB];  // phase 1: yF yL m11 mLL m1L ts; reduction: L U r 1/B; x
+  // per (partition, mode): y_1, y_len, (M^-1)_11, (M^-1)_len,len,
+  // (M^-1)_1,len, t of the separator row, then the separator value; padded
+  // against bank conflicts when the separator threads read a line's partitions
+  __shared__ double sh[6][P][TB + 1];
   __shared__ double red[16];
   k_thomas_body<S, TB, P, MAXM, EXACT, PF, HwGrid>(HwGrid{}, g, rm, t, Puse, partials, st, gate, ntx, ntiles, sh, red);
+}
+
+// Compiled variants of the tridiagonal kernel: TB modes times P partitions
+// per block and the rows of a partition (an upper bound, or the exact count
+// when every partition has it, nL = P * rows).  Fewer partitions mean fewer
+// reduction steps and less repeated pivot work; smaller blocks let several
+// run on one CU, so the barriers of one overlap the arithmetic of another.
+// Measured on batches of cubes (float32 rows, microseconds per solve of the
+// whole batch): 64^3 x 16: 47 (32 x 32) -> 18 (32 x 8); 96^3 x 12: 139 ->
+// 32 (32 x 8); 128^3 x 8: 96 -> 36 (32 x 8); 160^3 x 6: 208 -> 70 (16 x 16);
+// 256^3 x 2: 113 -> 70 (32 x 16); 512^3: 32 x 32 stays the fastest.  Float64
+// rows: 32 x 8 up to 128, 16 x 16 at 160, 32 x 16 at 256, 16 x 32 beyond.
+struct ThomasVariant {
+  int tb, p, rows;
+  bool exact;
+  constexpr int threads() const { return tb * p; }
+};
+template <class S> struct ThomasVariants;
+// Float32 rows stop at partitions of 16 rows (load axes up to 512): the
+// 32-row variant (1024 threads, 193 spilled registers) faulted on its first
+// run and is not compiled.
+template <> struct ThomasVariants<float> {
+  static constexpr ThomasVariant v[] = {
+      {32, 32, 16, true}, {32, 32, 8, true},   {32, 32, 5, true},   {32, 32, 4, true},  {32, 32, 3, true},
+      {32, 32, 2, true},  {32, 32, 4, false},  {32, 32, 8, false},  {32, 32, 16, false},
+      {32, 8, 16, true},  {32, 8, 12, true},   {32, 8, 8, true},    {32, 8, 6, true},   {32, 8, 4, false},
+      {32, 8, 8, false},  {32, 8, 16, false},
+      {16, 16, 16, true}, {16, 16, 10, true},  {16, 16, 4, false},  {16, 16, 8, false}, {16, 16, 16, false},
+      {64, 8, 16, true},  {64, 8, 12, true},   {64, 8, 8, true},    {64, 8, 6, true},   {64, 8, 4, false},
+      {64, 8, 8, false},  {64, 8, 16, false},
+      {32, 16, 16, true}, {32, 16, 10, true},  {32, 16, 4, false},  {32, 16, 8, false}, {32, 16, 16, false}};
+  static constexpr int n = sizeof(v) / sizeof(v[0]);
+};
+template <> struct ThomasVariants<double> {
+  static constexpr ThomasVariant v[] = {
+      {16, 32, 16, true}, {16, 32, 8, true},   {16, 32, 5, true},   {16, 32, 4, true},  {16, 32, 3, true},
+      {16, 32, 2, true},  {16, 32, 4, false},  {16, 32, 8, false},  {16, 32, 16, false}, {16, 32, 32, false},
+      {16, 32, 64, false},
+      {32, 8, 16, true},  {32, 8, 12, true},   {32, 8, 8, true},    {32, 8, 6, true},   {32, 8, 4, false},
+      {32, 8, 8, false},  {32, 8, 16, false},
+      {16, 16, 16, true}, {16, 16, 10, true},  {16, 16, 4, false},  {16, 16, 8, false}, {16, 16, 16, false},
+      {32, 16, 16, true}, {32, 16, 10, true},  {32, 16, 4, false},  {32, 16, 8, false}, {32, 16, 16, false}};
+  static constexpr int n = sizeof(v) / sizeof(v[0]);
+};
+
+// f(std::integral_constant<int, i>) for the variant index i == idx (none when
+// idx is out of range); the caller reads ThomasVariants<S>::v[i] as constants.
+template <class S, int I = 0, class F>
+__host__ __device__ __forceinline__ void with_thomas_variant(int idx, F&& f) {
+  if constexpr (I < ThomasVariants<S>::n) {
+    if (idx == I) f(std::integral_constant<int, I>{});
+    else with_thomas_variant<S, I + 1>(idx, static_cast<F&&>(f));
+  }
 }
 
 
@@ -2164,39 +2277,25 @@ template <class S> struct ThomasArgs {
   double* partials;
   const DevState* st;
   int ntx, ntiles;
-  int variant;  // partition rows (2, 3, 4, 5, 8, 16) + 100 when every partition has them exactly
+  int variant;  // index into ThomasVariants<S> (the launch's own)
 };
 template <class S> struct ThomasMulti { ThomasArgs<S> a[kMaxGroups]; };
 
-// Partition lengths of the multi-group tridiagonal kernel: exact 2, 3, 4,
-// 5, 8, 16 and guarded 4, 8, 16 (load axes up to 512).
-__host__ __device__ constexpr int thomas_variant(int maxm, bool exact) { return maxm + (exact ? 100 : 0); }
-
-template <class S, int TB, int P>
-__global__ __launch_bounds__(TB* P, 4) void k_thomas_multi(GroupMap gm, ThomasMulti<S> m, int gate) {
-  __shared__ double sh[6][P][TB];
+// The groups of one launch share its variant I (a launch per variant the
+// groups use): one body per kernel keeps each variant's register allocation
+// that of its single-group kernel (a kernel holding several bodies takes
+// the register pressure of the worst and spills in all of them).
+template <class S, int I>
+__global__ __launch_bounds__(ThomasVariants<S>::v[I].threads(), 4) void k_thomas_multi(GroupMap gm, ThomasMulti<S> m,
+                                                                                       int gate) {
+  constexpr ThomasVariant v = ThomasVariants<S>::v[I];
+  constexpr bool PF = (v.exact && sizeof(S) == 4) || v.rows <= 8;
+  __shared__ double sh[6][v.p][v.tb + 1];
   __shared__ double red[16];
   SubGrid sg;
   const auto& x = m.a[gm.find(sg)];
-  auto run = [&](auto mm, auto ex) {
-    constexpr int MAXM = decltype(mm)::value;
-    constexpr bool EXACT = decltype(ex)::value;
-    k_thomas_body<S, TB, P, MAXM, EXACT, ((EXACT && sizeof(S) == 4) || MAXM <= 8), SubGrid>(
-        sg, x.g, x.rm, x.t, x.Puse, x.partials, x.st, gate, x.ntx, x.ntiles, sh, red);
-  };
-  using T_ = std::true_type;
-  using F_ = std::false_type;
-  switch (x.variant) {
-    case thomas_variant(16, true): run(std::integral_constant<int, 16>{}, T_{}); break;
-    case thomas_variant(8, true): run(std::integral_constant<int, 8>{}, T_{}); break;
-    case thomas_variant(5, true): run(std::integral_constant<int, 5>{}, T_{}); break;
-    case thomas_variant(4, true): run(std::integral_constant<int, 4>{}, T_{}); break;
-    case thomas_variant(3, true): run(std::integral_constant<int, 3>{}, T_{}); break;
-    case thomas_variant(2, true): run(std::integral_constant<int, 2>{}, T_{}); break;
-    case thomas_variant(4, false): run(std::integral_constant<int, 4>{}, F_{}); break;
-    case thomas_variant(8, false): run(std::integral_constant<int, 8>{}, F_{}); break;
-    default: run(std::integral_constant<int, 16>{}, F_{}); break;
-  }
+  k_thomas_body<S, v.tb, v.p, v.rows, v.exact, PF, SubGrid>(sg, x.g, x.rm, x.t, x.Puse, x.partials, x.st, gate, x.ntx,
+                                                             x.ntiles, sh, red);
 }
 
 struct FinArgs {

@@ -61,6 +61,16 @@ def test_workspace_size_rejects_bad_shapes(shape, axis):
     assert e.value.status in (-1, -6)
 
 
+def test_mixed_form_load_axis_limit():
+    """The mixed form's tridiagonal kernel holds partitions of at most 16
+    rows (load axis 512); the float64 form goes to 2048."""
+    etc.etc_workspace_size((512, 4, 4), "float32", 0, precision="mixed")
+    etc.etc_workspace_size((2048, 4, 4), "float64", 0)
+    with pytest.raises(etc.EtcError) as e:
+        etc.etc_workspace_size((513, 4, 4), "float32", 0, precision="mixed")
+    assert e.value.status == -6
+
+
 def test_setup_rejects_bad_arguments_without_device():
     lib = etc.load_library()
     n = (ctypes.c_int64 * 3)(4, 4, 4)

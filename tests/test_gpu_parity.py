@@ -97,6 +97,60 @@ def test_preconditioner_matches_oracle_fp64(shape):
     plan.close()
 
 
+# Every compiled tridiagonal block shape (modes x partitions per line) on
+# load axes that hit its exact partition lengths and its ragged (guarded)
+# ones; b = 37 leaves a partial tile of modes for every shape.
+THOMAS_LENGTHS = {
+    8: [10, 20, 33, 48, 64, 96, 100, 128],
+    16: [48, 100, 160, 200, 256],
+    32: [64, 96, 100, 128, 160, 200, 256, 300, 512, 700, 1500],
+}
+THOMAS_SHAPES = {"fp64": [(32, 8), (16, 16), (32, 16), (16, 32)],
+                 "mixed": [(32, 8), (16, 16), (64, 8), (32, 16), (32, 32)]}
+# The float32 32-row partition variant (load axes 513-1024 in the mixed form)
+# faulted on its first run with no cause found in its indexing; it is no
+# longer compiled and the mixed form refuses load axes above 512.
+_NO_F32_LONG = pytest.mark.skip(reason="float32 partitions of more than 16 rows are switched off (the 32-row "
+                                       "variant faulted; mixed-form load axes stop at 512)")
+THOMAS_CASES = [pytest.param(prec, tb, p, nl, marks=_NO_F32_LONG) if prec == "mixed" and nl > 512
+                else (prec, tb, p, nl)
+                for prec, shapes in THOMAS_SHAPES.items() for tb, p in shapes for nl in THOMAS_LENGTHS[p]]
+
+
+@pytest.mark.parametrize("precision,tb,parts,nl", THOMAS_CASES)
+def test_preconditioner_every_tridiagonal_shape(precision, tb, parts, nl):
+    shape = (nl, 5, 37)
+    kap = lognormal(shape, seed=nl + tb + parts, sigma=0.7)
+    mixed = precision == "mixed"
+    tdt = torch.float32 if mixed else torch.float64
+    print(f"tridiagonal {tb}x{parts} {precision} nL={nl}", flush=True)
+    plan = etc.etc_setup(dev(kap, tdt), 0, precision=precision, thomas_shape=(tb, parts))
+    assert etc.etc_launch_info(plan)["thomas_shape"] == (tb, parts)
+    pb = O.make_problem(kap.astype(np.float32).astype(np.float64) if mixed else kap, 0)
+    r = np.random.default_rng(nl).standard_normal(pb.shape)
+    if mixed:
+        r = r.astype(np.float32)
+    z, rz = etc.etc_apply_Minv(plan, dev(r, tdt), want_dot=True)
+    plan.close()
+    ref = O.apply_Aref_inv(r.astype(np.float64), O.kref_mid(pb))
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    rz_ref = float(np.vdot(r.astype(np.float64), ref))
+    assert err < (1e-5 if mixed else 1e-11), err
+    assert abs(rz - rz_ref) < (1e-5 if mixed else 1e-10) * abs(rz_ref)
+
+
+def test_tridiagonal_shape_that_does_not_hold_the_axis_is_rejected():
+    kap = dev(lognormal((200, 4, 4), seed=1))
+    for shape in ((32, 8), (7, 7), (32, 32)):
+        with pytest.raises(RuntimeError):
+            etc.etc_setup(kap, 0, thomas_shape=shape)  # (32, 32) is float32 only
+    etc.etc_setup(kap, 0, thomas_shape=(16, 32)).close()
+    for nl, want in ((64, (32, 8)), (128, (32, 8)), (160, (16, 16)), (256, (32, 16)), (257, (16, 32))):
+        plan = etc.etc_setup(dev(lognormal((nl, 4, 4), seed=2)), 0)
+        assert etc.etc_launch_info(plan)["thomas_shape"] == want, nl
+        plan.close()
+
+
 @pytest.mark.parametrize("shape", [(96, 8, 12), (256, 4, 16), (3, 256, 160), (2, 48, 512), (300, 3, 5), (64, 6, 40),
                                    (33, 16, 16), (4, 128, 64), (5, 512, 32), (3, 512, 40), (2, 64, 160)])
 def test_preconditioner_mixed_shapes(shape):
@@ -552,6 +606,7 @@ def test_autotuned_plan_reaches_the_same_solution():
                              autotune=True)
         info = etc.etc_launch_info(plan)
         assert info["tuned"] and 1 <= info["kchunk"] <= 40 and info["thomas_blocks"] >= 1
+        assert info["thomas_shape"] in [(32, 8), (16, 16), (32, 16), (64, 8), (32, 32), (16, 32)]
         etc.etc_solve(plan)
         k = etc.etc_keff(plan)["keff"]
         plan.close()
