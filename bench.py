@@ -438,7 +438,12 @@ def main():
     if not args.no_2000 and args.n == 512:
         line["spheres512_2000"] = leg_2000(torch, etc, rvegen, args, forms)
     if ens is not None:
-        line["ensemble"] = ensemble_record(torch, etc, rvegen, args, ens, "mixed")
+        # both ensemble forms: per-shape batch plans on concurrent streams and
+        # one plan whose every kernel of a pass is one launch for all RVEs
+        rec = ensemble_record(torch, etc, rvegen, args, ens, "mixed", "plans")
+        one = ensemble_record(torch, etc, rvegen, args, ens, "mixed", "launch")
+        rec["one_launch"] = {k: one[k] for k in ("rves_per_s", "s_per_ensemble", "iters_min_max", "all_ok", "plans")}
+        line["ensemble"] = rec
         del ens
     if not args.no_cpu:
         print("bench: cpu oracle sample", file=sys.stderr, flush=True)

@@ -251,6 +251,11 @@ etc_status etc_keff(etc_plan* plan, double* k_out, double* k_in, double* k_energ
  * when want_grad is set).  Synchronises. */
 etc_status etc_grad(etc_plan* plan, double* dk_dkappa);
 
+/* etc_grad with the gradient written as `out_dt` (ETC_F64 or ETC_F32, e.g.
+ * the dtype kappa was given in): the same float64 arithmetic, rounded once
+ * on the store.  ETC_E_INVALID for another dtype. */
+etc_status etc_grad_as(etc_plan* plan, void* dk_dkappa, etc_dtype out_dt);
+
 /* Copy the solution p into `p` (device, user layout, float64, caller-owned). */
 etc_status etc_get_solution(const etc_plan* plan, double* p);
 

@@ -113,6 +113,7 @@ _SYMBOLS = {
                                 ctypes.POINTER(ctypes.c_double)]),
     "etc_get_solution": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "etc_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "etc_grad_as": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "etc_residual_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_int)]),
     "etc_apply_A": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -640,11 +641,16 @@ def etc_residual_history(plan: Plan, cap: int = 100000):
     return [buf[i] for i in range(n.value)]
 
 
-def etc_grad(plan: Plan):
-    """dK_out/dkappa (float64, user layout) by the adjoint method."""
+def etc_grad(plan: Plan, dtype=None):
+    """dK_out/dkappa (user layout) by the adjoint method, float64 by default
+    or ``dtype`` = torch.float32 (e.g. kappa's own), rounded once on the
+    device (etc_grad_as)."""
     torch = _torch()
-    g = torch.empty(plan.shape, dtype=torch.float64, device=plan.device)
-    _check(load_library().etc_grad(plan.handle, g.data_ptr()))
+    dtype = torch.float64 if dtype is None else dtype
+    if dtype not in (torch.float64, torch.float32):
+        raise ValueError("dtype must be torch.float64 or torch.float32")
+    g = torch.empty(plan.shape, dtype=dtype, device=plan.device)
+    _check(load_library().etc_grad_as(plan.handle, g.data_ptr(), _DTYPE["float64" if dtype == torch.float64 else "float32"]))
     return g
 
 
@@ -661,18 +667,25 @@ class KeffFunction:
             class _Keff(torch.autograd.Function):
                 @staticmethod
                 def forward(ctx, kappa, axis, p_in, p_out, precision, rtol):
-                    plan = etc_setup(kappa.detach(), axis, p_in, p_out, precision, rtol, want_grad=True)
-                    etc_solve(plan)
-                    k = etc_keff(plan)["keff"]
-                    ctx.plan = plan
-                    ctx.kdtype = kappa.dtype
+                    # The adjoint solve runs here, while the plan exists, and
+                    # only the gradient (kappa's dtype) is kept for backward:
+                    # the plan's workspace is freed before forward returns.
+                    want = bool(ctx.needs_input_grad[0])
+                    plan = etc_setup(kappa.detach(), axis, p_in, p_out, precision, rtol, want_grad=want)
+                    try:
+                        etc_solve(plan)
+                        k = etc_keff(plan)["keff"]
+                        g = etc_grad(plan, kappa.dtype) if want else None
+                    finally:
+                        plan.close()
+                    if want:
+                        ctx.save_for_backward(g)
                     return torch.tensor(k, dtype=torch.float64, device=kappa.device)
 
                 @staticmethod
                 def backward(ctx, grad_out):
-                    g = etc_grad(ctx.plan)
-                    ctx.plan.close()
-                    return (grad_out * g).to(ctx.kdtype), None, None, None, None, None
+                    (g,) = ctx.saved_tensors
+                    return (grad_out.to(g.dtype) * g), None, None, None, None, None
 
             cls._cls = _Keff
         return cls._cls

@@ -995,8 +995,9 @@ template <class S> struct Ops {
     return ETC_OK;
   }
 
-  static etc_status grad(etc_plan* P, double* out_user, double c) {
-    k_grad<S><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, P->padj, kap(P), c, P->axis, out_user);
+  template <class O>
+  static etc_status grad(etc_plan* P, O* out_user, double c) {
+    k_grad<S, O><<<P->lc.gridStride, kThreads, 0, P->stream>>>(P->g, P->p, P->padj, kap(P), c, P->axis, out_user);
     LAUNCHCHK("grad");
     return ETC_OK;
   }
@@ -1271,13 +1272,14 @@ template <class S> struct Ops {
   }
 
   // dK/dkappa of one instance of a batch plan into `out` (user layout)
-  static etc_status grad_instance(etc_plan* P, int inst, double* out, double c) {
+  template <class O>
+  static etc_status grad_instance(etc_plan* P, int inst, O* out, double c) {
     Geo g1 = P->g;
     g1.nseg = 1;
     const int64_t off = (int64_t)inst * P->g.V;
     Kap<S> k = kap(P);
     k.shift(off);
-    k_grad<S><<<dim3(P->lc.nStride, 1), kThreads, 0, P->stream>>>(g1, P->p + off, P->padj + off, k, c, P->axis, out);
+    k_grad<S, O><<<dim3(P->lc.nStride, 1), kThreads, 0, P->stream>>>(g1, P->p + off, P->padj + off, k, c, P->axis, out);
     LAUNCHCHK("grad");
     return ETC_OK;
   }
@@ -2167,7 +2169,8 @@ etc_status etc_residual_history(const etc_plan* P, double* hist, int cap, int* c
   return ETC_OK;
 }
 
-static etc_status grad_ensemble(etc_plan* E, double* out) {
+extern "C++" template <class O>
+static etc_status grad_ensemble(etc_plan* E, O* out) {
   for (etc_plan* G : E->groups)
     if (!G->padj) return fail(ETC_E_STATE, "etc_grad needs a plan made with want_grad = 1");
   if (!E->solved) return fail(ETC_E_STATE, "etc_grad before a successful etc_solve");
@@ -2210,9 +2213,13 @@ static etc_status grad_ensemble(etc_plan* E, double* out) {
   return ETC_OK;
 }
 
-etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
+etc_status etc_grad(etc_plan* P, double* dk_dkappa) { return etc_grad_as(P, dk_dkappa, ETC_F64); }
+
+etc_status etc_grad_as(etc_plan* P, void* dk_dkappa, etc_dtype out_dt) {
   if (!P || !dk_dkappa) return fail(ETC_E_INVALID, "NULL argument");
-  if (!P->groups.empty()) return grad_ensemble(P, dk_dkappa);
+  if (out_dt != ETC_F64 && out_dt != ETC_F32) return fail(ETC_E_INVALID, "bad output dtype");
+  if (!P->groups.empty())
+    return out_dt == ETC_F64 ? grad_ensemble(P, (double*)dk_dkappa) : grad_ensemble(P, (float*)dk_dkappa);
   if (!P->padj) return fail(ETC_E_STATE, "etc_grad needs a plan made with want_grad = 1");
   if (!P->solved) return fail(ETC_E_STATE, "etc_grad before a successful etc_solve");
   // adjoint solve: the primal system with Dirichlet pair (0, 1), solution into padj
@@ -2234,7 +2241,10 @@ etc_status etc_grad(etc_plan* P, double* dk_dkappa) {
   P->solved = true;
   if (s != ETC_OK && s != ETC_NOT_CONVERGED) return s;
   const double c = (double)g0.nL / ((double)g0.na * (double)g0.nb * (g0.p_in - g0.p_out));
-  s = (P->prec == ETC_MIXED) ? Ops<float>::grad(P, dk_dkappa, c) : Ops<double>::grad(P, dk_dkappa, c);
+  if (out_dt == ETC_F64)
+    s = (P->prec == ETC_MIXED) ? Ops<float>::grad(P, (double*)dk_dkappa, c) : Ops<double>::grad(P, (double*)dk_dkappa, c);
+  else
+    s = (P->prec == ETC_MIXED) ? Ops<float>::grad(P, (float*)dk_dkappa, c) : Ops<double>::grad(P, (float*)dk_dkappa, c);
   if (s) return s;
   HIPCHK(hipStreamSynchronize(P->stream));
   return ETC_OK;

@@ -1991,11 +1991,11 @@ __global__ __launch_bounds__(256) void k_energy(Geo g, const double* __restrict_
 //               - sum_{faces F of v} dkappa_F/dkappa_v (p_v - p_n)(lambda_v - lambda_n)
 //               - [v first] 2 fL (p_v - p_in) lambda_v - [v last] 2 fL (p_v - p_out) lambda_v,
 // dkappa_F/dkappa_v = f_d 2 kappa_n^2 / (kappa_v + kappa_n)^2 for a
-// harmonic-mean face.  Reads the canonical layout, writes `out` in the
-// user layout of load axis `axis`; double arithmetic.
-template <class S>
+// harmonic-mean face.  Reads the canonical layout, writes `out` (type O) in
+// the user layout of load axis `axis`; double arithmetic.
+template <class S, class O>
 __global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ p, const double* __restrict__ phi,
-                                              Kap<S> kp, double c, int axis, double* __restrict__ out) {
+                                              Kap<S> kp, double c, int axis, O* __restrict__ out) {
   {
     const int64_t off = (int64_t)blockIdx.y * g.V;
     p += off;
@@ -2024,7 +2024,7 @@ __global__ __launch_bounds__(256) void k_grad(Geo g, const double* __restrict__ 
     if (k == 0) gv -= 2.0 * g.fL * (pv - g.p_in) * lv;
     if (k == g.nL - 1) gv += 2.0 * c * (pv - g.p_out) - 2.0 * g.fL * (pv - g.p_out) * lv;
     const int64_t ui = axis == 0 ? i : (axis == 1 ? (a * g.nL + k) * g.nb + b : (a * g.nb + b) * g.nL + k);
-    out[ui] = gv;
+    out[ui] = (O)gv;
   }
 }
 

@@ -354,8 +354,22 @@ def test_autograd_function():
     plan = etc.etc_setup(dev(kap), 0, rtol=1e-12, want_grad=True)
     etc.etc_solve(plan)
     g = etc.etc_grad(plan)
+    # etc_grad_as: the same float64 gradient rounded once to float32
+    assert torch.equal(etc.etc_grad(plan, torch.float32), g.to(torch.float32))
     plan.close()
     assert torch.allclose(gx, 3.0 * g, rtol=1e-10, atol=1e-14)
+    # float32 kappa: the gradient comes back in kappa's dtype; without
+    # requires_grad no adjoint solve runs and K is the same
+    x32 = dev(kap, torch.float32).requires_grad_(True)
+    (g32,) = torch.autograd.grad(etc.keff(x32, 0, rtol=1e-12), x32)
+    assert g32.dtype == torch.float32 and g32.shape == x32.shape
+    ref32 = etc.etc_setup(dev(kap, torch.float32), 0, rtol=1e-12, want_grad=True)
+    etc.etc_solve(ref32)
+    g_ref = etc.etc_grad(ref32, torch.float32)
+    ref32.close()
+    assert torch.equal(g32, g_ref)
+    with torch.no_grad():
+        assert abs(float(etc.keff(dev(kap), 0, rtol=1e-12)) - float(k)) <= 1e-14 * float(k)
 
 
 def test_grad_requires_want_grad():
