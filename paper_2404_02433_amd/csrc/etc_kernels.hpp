@@ -1808,7 +1808,18 @@ __device__ __forceinline__ void k_fin_body(const BG bg, int op, const double* __
     if (st->done) return;
   }
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+  // eight loads in flight before the first add, the adds in the order of a
+  // plain strided loop (the same sum bit for bit)
+  const int step = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * step < n; i += 8 * step) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = partials[i + u * step];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += x[u];
+  }
+  for (; i < n; i += step) v += partials[i];
   const double s = block_sum(v, red);
   if (threadIdx.x != 0) return;
   switch (op) {
