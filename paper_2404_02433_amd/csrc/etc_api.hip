@@ -1069,9 +1069,11 @@ template <class S> struct Ops {
   // kernel per group.
   static etc_status multi_prepare(etc_plan* E) {
     // Each group keeps the persistent grid it would have alone (blocks per
-    // instance filling the device): measured on the 64-RVE GRF ensemble, 139
-    // RVEs/s against 123 with one block per tile or with the device's
-    // resident blocks shared out in proportion to each group's rows.
+    // instance filling the device): on the 64-RVE GRF ensemble (edges
+    // 48-160) that ran faster than one block per tile, or than the device's
+    // resident blocks shared out in proportion to each group's rows
+    // (139 against 123 RVEs/s, timed with 32 partitions per line in every
+    // group).
     E->multi_thomas_per.clear();
     for (const etc_plan* P : E->groups) E->multi_thomas_per.push_back((int)P->lc.gridThomas.x);
     return multi_lds(E);
