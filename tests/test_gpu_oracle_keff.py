@@ -9,10 +9,11 @@ in the launch configuration the benchmark times:
 
 * float64 form at rtol 1e-6 against the oracle run to the same rtol with the
   same reference parameters and start: pass count within one, K within
-  1e-6 relative (the float64 bar).  Over a few tens of passes the two agree
-  to about 1e-11; over 140 or more passes of a contrast-1e3 field, rounding
-  differences between the FFT-based transforms and the oracle's O(N^2)
-  definitions move the stopping iterate by up to a few 1e-7;
+  1e-8 relative where the oracle stops within 100 passes (measured: at most
+  4e-12 on the 512^3 sphere RVEs, 1e-13 on the spheroids), 1e-6 beyond:
+  over 140 or more passes of a contrast-1e3 field, rounding differences
+  between the FFT-based transforms and the oracle's O(N^2) definitions move
+  the stopping iterate by up to a few 1e-7 (3e-7 on the 48^3 ensemble RVE);
 * float64 and mixed forms at rtol 1e-6 against the oracle's solution of
   A p = b: K within 1e-5 relative (the scope's target bar).  Stopping at
   relres 1e-6 itself leaves up to a few 1e-6 in K: the oracle's own rtol-1e-6
@@ -74,7 +75,8 @@ def test_keff_matches_oracle(name, rve_inputs):
     print(f"golden {name}: fp64 rel diff vs oracle traj {abs(f64['keff'] - traj['keff']) / traj['keff']:.2e}, "
           f"vs solution {abs(f64['keff'] - truth['keff']) / truth['keff']:.2e}", flush=True)
     assert abs(f64["iters"] - traj["iters"]) <= 1
-    assert abs(f64["keff"] - traj["keff"]) <= 1e-6 * traj["keff"]
+    bar = 1e-8 if traj["iters"] <= 100 else 1e-6
+    assert abs(f64["keff"] - traj["keff"]) <= bar * traj["keff"]
     assert abs(f64["keff"] - truth["keff"]) <= 1e-5 * truth["keff"]
     mixed = run(kap, axis, "mixed")
     print(f"golden {name}: mixed K={mixed['keff']:.12g} iters={mixed['iters']} "
