@@ -114,7 +114,8 @@ _NO_F32_LONG = pytest.mark.skip(reason="float32 partitions of more than 16 rows 
                                        "variant faulted; mixed-form load axes stop at 512)")
 THOMAS_CASES = [pytest.param(prec, tb, p, nl, marks=_NO_F32_LONG) if prec == "mixed" and nl > 512
                 else (prec, tb, p, nl)
-                for prec, shapes in THOMAS_SHAPES.items() for tb, p in shapes for nl in THOMAS_LENGTHS[p]]
+                for prec, shapes in THOMAS_SHAPES.items() for tb, p in shapes
+                for nl in THOMAS_LENGTHS[p] + ([512] if (tb, p) == (32, 16) else [])]  # 32x16: 16 partitions of 32
 
 
 @pytest.mark.parametrize("precision,tb,parts,nl", THOMAS_CASES)
@@ -145,7 +146,8 @@ def test_tridiagonal_shape_that_does_not_hold_the_axis_is_rejected():
         with pytest.raises(RuntimeError):
             etc.etc_setup(kap, 0, thomas_shape=shape)  # (32, 32) is float32 only
     etc.etc_setup(kap, 0, thomas_shape=(16, 32)).close()
-    for nl, want in ((64, (32, 8)), (128, (32, 8)), (160, (16, 16)), (256, (32, 16)), (257, (16, 32))):
+    for nl, want in ((64, (32, 8)), (128, (32, 8)), (160, (16, 16)), (256, (32, 16)), (257, (16, 32)),
+                     (512, (32, 16))):
         plan = etc.etc_setup(dev(lognormal((nl, 4, 4), seed=2)), 0)
         assert etc.etc_launch_info(plan)["thomas_shape"] == want, nl
         plan.close()
