@@ -260,11 +260,11 @@ template <class S> int thomas_pick(int tb, int p, int nL) {
 
 // Block shape of the tridiagonal kernel by load-axis length, from timings of
 // every compiled shape on batches of cubes (the autotuner may pick another):
-// 32 x 8 up to 128 rows, 16 x 16 up to 192, 32 x 16 up to 256 and at 512
-// (16 partitions of 32 rows), else 32 partitions of 32 (float32) or 16
-// (float64) modes.
+// 32 x 8 up to 128 rows and at 160 and 256 (8 partitions of 20 or 32 rows),
+// 16 x 16 up to 192, 32 x 16 up to 256 and at 512 (16 partitions of 32
+// rows), else 32 partitions of 32 (float32) or 16 (float64) modes.
 void thomas_default_shape(int nL, size_t elt, int& tb, int& p) {
-  if (nL <= 128) tb = 32, p = 8;
+  if (nL <= 128 || nL == 160 || nL == 256) tb = 32, p = 8;
   else if (nL <= 192) tb = 16, p = 16;
   else if (nL <= 256 || nL == 512) tb = 32, p = 16;
   else tb = elt == 4 ? 32 : 16, p = kThomasP;
@@ -1235,9 +1235,8 @@ template <class S> struct Ops {
       with_thomas_variant<S>(var, [&](auto ic) {
         constexpr int I = decltype(ic)::value;
         // ensemble load axes stop at 512: partitions of at most 16 rows, or
-        // exactly 32 (16 partitions of a 512-row axis)
-        if constexpr (ThomasVariants<S>::v[I].rows <= 16 ||
-                      (ThomasVariants<S>::v[I].exact && ThomasVariants<S>::v[I].rows == 32)) {
+        // exact partitions of more (20 or 32 rows)
+        if constexpr (ThomasVariants<S>::v[I].rows <= 16 || ThomasVariants<S>::v[I].exact) {
           k_thomas_multi<S, I><<<tot, ThomasVariants<S>::v[I].threads(), 0, E->stream>>>(gm, m, 1);
           launched = true;
         }

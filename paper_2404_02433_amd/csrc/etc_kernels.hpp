@@ -1749,16 +1749,20 @@ __global__ __launch_bounds__(TB* P, MINW) void k_thomas(Geo g, RefMedium rm, S* 
 // rows: 32 x 8 up to 128, 16 x 16 at 160, 32 x 16 at 256, 16 x 32 beyond.
 // At 512 rows, 32 x 16 with exact partitions of 32 rows (512 threads, up to
 // 256 registers, one block per CU) beats 32 partitions of 16: 281 against
-// 315 us (float32 rows) and 451 against 567 us (float64).
+// 315 us (float32 rows) and 451 against 567 us (float64).  Likewise 32 x 8
+// with exact partitions of 20 rows at 160 and of 32 at 256 (256 threads,
+// up to 256 registers): 160^3 x 6: 70 -> 52 us (float32), 93 -> 85
+// (float64); 256^3 x 2: 71 -> 64 us (float32), 109 -> 103 (float64).
 struct ThomasVariant {
   int tb, p, rows;
   bool exact;
   constexpr int threads() const { return tb * p; }
 };
 template <class S> struct ThomasVariants;
-// Float32 rows stop at partitions of 16 rows (load axes up to 512): the
-// 32-row variant (1024 threads, 193 spilled registers) faulted on its first
-// run and is not compiled.
+// Float32 guarded partitions stop at 16 rows (load axes up to 512): the
+// 32 x 32 variant of up to 32 rows (1024 threads, 193 spilled registers)
+// faulted on its first run and is not compiled.  Exact partitions of 20 and
+// 32 rows (at most 512 threads) are.
 template <> struct ThomasVariants<float> {
   static constexpr ThomasVariant v[] = {
       {32, 32, 16, true}, {32, 32, 8, true},   {32, 32, 5, true},   {32, 32, 4, true},  {32, 32, 3, true},
@@ -1769,7 +1773,7 @@ template <> struct ThomasVariants<float> {
       {64, 8, 16, true},  {64, 8, 12, true},   {64, 8, 8, true},    {64, 8, 6, true},   {64, 8, 4, false},
       {64, 8, 8, false},  {64, 8, 16, false},
       {32, 16, 16, true}, {32, 16, 10, true},  {32, 16, 4, false},  {32, 16, 8, false}, {32, 16, 16, false},
-      {32, 16, 32, true}};
+      {32, 16, 32, true}, {32, 8, 20, true},   {32, 8, 32, true}};
   static constexpr int n = sizeof(v) / sizeof(v[0]);
 };
 template <> struct ThomasVariants<double> {
@@ -1781,7 +1785,7 @@ template <> struct ThomasVariants<double> {
       {32, 8, 8, false},  {32, 8, 16, false},
       {16, 16, 16, true}, {16, 16, 10, true},  {16, 16, 4, false},  {16, 16, 8, false}, {16, 16, 16, false},
       {32, 16, 16, true}, {32, 16, 10, true},  {32, 16, 4, false},  {32, 16, 8, false}, {32, 16, 16, false},
-      {32, 16, 32, true}};
+      {32, 16, 32, true}, {32, 8, 20, true},   {32, 8, 32, true}};
   static constexpr int n = sizeof(v) / sizeof(v[0]);
 };
 

@@ -110,12 +110,15 @@ THOMAS_SHAPES = {"fp64": [(32, 8), (16, 16), (32, 16), (16, 32)],
 # The float32 32-row partition variant (load axes 513-1024 in the mixed form)
 # faulted on its first run with no cause found in its indexing; it is no
 # longer compiled and the mixed form refuses load axes above 512.
-_NO_F32_LONG = pytest.mark.skip(reason="float32 partitions of more than 16 rows are switched off (the 32-row "
-                                       "variant faulted; mixed-form load axes stop at 512)")
+_NO_F32_LONG = pytest.mark.skip(reason="float32 guarded partitions of more than 16 rows are switched off (the "
+                                       "32x32 variant of up to 32 rows faulted; mixed-form load axes stop at 512)")
+# exact partitions of more than 16 rows: 32x16 at 512 (32 rows), 32x8 at 160
+# and 256 (20 and 32 rows)
+_EXACT_LONG = {(32, 16): [512], (32, 8): [160, 256]}
 THOMAS_CASES = [pytest.param(prec, tb, p, nl, marks=_NO_F32_LONG) if prec == "mixed" and nl > 512
                 else (prec, tb, p, nl)
                 for prec, shapes in THOMAS_SHAPES.items() for tb, p in shapes
-                for nl in THOMAS_LENGTHS[p] + ([512] if (tb, p) == (32, 16) else [])]  # 32x16: 16 partitions of 32
+                for nl in THOMAS_LENGTHS[p] + _EXACT_LONG.get((tb, p), [])]
 
 
 @pytest.mark.parametrize("precision,tb,parts,nl", THOMAS_CASES)
@@ -146,8 +149,8 @@ def test_tridiagonal_shape_that_does_not_hold_the_axis_is_rejected():
         with pytest.raises(RuntimeError):
             etc.etc_setup(kap, 0, thomas_shape=shape)  # (32, 32) is float32 only
     etc.etc_setup(kap, 0, thomas_shape=(16, 32)).close()
-    for nl, want in ((64, (32, 8)), (128, (32, 8)), (160, (16, 16)), (256, (32, 16)), (257, (16, 32)),
-                     (512, (32, 16))):
+    for nl, want in ((64, (32, 8)), (128, (32, 8)), (150, (16, 16)), (160, (32, 8)), (200, (32, 16)),
+                     (256, (32, 8)), (257, (16, 32)), (512, (32, 16))):
         plan = etc.etc_setup(dev(lognormal((nl, 4, 4), seed=2)), 0)
         assert etc.etc_launch_info(plan)["thomas_shape"] == want, nl
         plan.close()
