@@ -64,13 +64,41 @@ def iteration_bytes_per_voxel(es: int, mixed: bool, refine_every: int) -> float:
     return b
 
 
+def code_tokens(src: str) -> str:
+    """C++ source without its comments and with runs of white space folded to
+    one blank (string and character literals kept as they are), so that a
+    change of comments or layout alone leaves the hash of the kernels as it
+    was."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash() -> str:
+    """Hash of the kernel and library sources (code only, see code_tokens)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2404_02433_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 

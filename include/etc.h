@@ -103,8 +103,9 @@ typedef struct {
   int thomas_parts;      /* partitions per line, both 0 (default) for the built-in
                             choice by load-axis length; compiled shapes (float32 /
                             float64 rows): 32x8, 16x16, 32x16 and 32x32 / 16x32, plus
-                            64x8 (float32).  32x8 holds load axes up to 128, 16x16
-                            and 32x16 up to 256 (32x16 also exactly 512), the
+                            64x8 (float32).  32x8 holds load axes up to 128 (and
+                            exactly 160 and 256), 16x16 and 32x16 up to 256 (32x16
+                            also exactly 512), the
                             32-partition shapes up to 2048 (512 in the mixed form);
                             etc_setup returns ETC_E_UNSUPPORTED for a shape that is
                             not compiled or does not hold the load axis.  With

@@ -1745,7 +1745,7 @@ __global__ __launch_bounds__(TB* P, MINW) void k_thomas(Geo g, RefMedium rm, S* 
 // Measured on batches of cubes (float32 rows, microseconds per solve of the
 // whole batch): 64^3 x 16: 47 (32 x 32) -> 18 (32 x 8); 96^3 x 12: 139 ->
 // 32 (32 x 8); 128^3 x 8: 96 -> 36 (32 x 8); 160^3 x 6: 208 -> 70 (16 x 16);
-// 256^3 x 2: 113 -> 70 (32 x 16); 512^3: 32 x 32 stays the fastest.  Float64
+// 256^3 x 2: 113 -> 70 (32 x 16); 512^3: 32 x 32 stays the fastest of these.  Float64
 // rows: 32 x 8 up to 128, 16 x 16 at 160, 32 x 16 at 256, 16 x 32 beyond.
 // At 512 rows, 32 x 16 with exact partitions of 32 rows (512 threads, up to
 // 256 registers, one block per CU) beats 32 partitions of 16: 281 against
