@@ -99,12 +99,13 @@ def test_one_launch_ensemble_solution_layout_and_single_solves():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_one_launch_ensemble_spans_tridiagonal_block_sizes(precision):
-    """Load axes of 40, 160, 200 and 300 voxels take tridiagonal blocks of
-    32x8, 16x16, 32x16 and 32 partitions (256, 256, 512 and 1024 / 512
-    threads): one multi-group launch per variant.  K_eff against the oracle
-    (float64 1e-9, mixed 1e-4) and the same pass counts and K_eff as the
-    RVEs' own batch plans."""
-    shapes = [(40, 8, 9), (160, 6, 7), (200, 5, 6), (300, 5, 5), (40, 8, 9)]
+    """Load axes of 40, 160, 150, 200 and 300 voxels take tridiagonal blocks
+    of 32x8 (ragged partitions of up to 8 rows; exact ones of 20), 16x16,
+    32x16 and 32 partitions (256, 256, 256, 512 and 1024 / 512 threads): one
+    multi-group launch per variant.  K_eff against the oracle (float64 1e-9,
+    mixed 1e-4) and the same pass counts and K_eff as the RVEs' own batch
+    plans."""
+    shapes = [(40, 8, 9), (160, 6, 7), (150, 6, 7), (200, 5, 6), (300, 5, 5), (40, 8, 9)]
     rng = np.random.default_rng(77)
     kaps = [np.exp(0.8 * rng.standard_normal(s)) for s in shapes]
     dtype = torch.float32 if precision == "mixed" else torch.float64
