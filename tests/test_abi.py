@@ -62,8 +62,8 @@ def test_workspace_size_rejects_bad_shapes(shape, axis):
 
 
 def test_mixed_form_load_axis_limit():
-    """The mixed form's tridiagonal kernel holds partitions of at most 16
-    rows (load axis 512); the float64 form goes to 2048."""
+    """The mixed form's guarded tridiagonal partitions hold at most 16 rows
+    (load axes up to 512); the float64 form goes to 2048."""
     etc.etc_workspace_size((512, 4, 4), "float32", 0, precision="mixed")
     etc.etc_workspace_size((2048, 4, 4), "float64", 0)
     with pytest.raises(etc.EtcError) as e:

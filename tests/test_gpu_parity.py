@@ -103,7 +103,7 @@ def test_preconditioner_matches_oracle_fp64(shape):
 THOMAS_LENGTHS = {
     8: [10, 20, 33, 48, 64, 96, 100, 128],
     16: [48, 100, 160, 200, 256],
-    32: [64, 96, 100, 128, 160, 200, 256, 300, 512, 700, 1500],
+    32: [64, 96, 100, 128, 160, 200, 256, 300, 512, 700, 1500, 2048],
 }
 THOMAS_SHAPES = {"fp64": [(32, 8), (16, 16), (32, 16), (16, 32)],
                  "mixed": [(32, 8), (16, 16), (64, 8), (32, 16), (32, 32)]}
