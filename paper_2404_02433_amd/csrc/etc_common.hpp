@@ -138,6 +138,13 @@ __device__ __forceinline__ double frcp(double u) {
 }
 // float32: the hardware reciprocal (1 ulp)
 __device__ __forceinline__ float frcp(float u) { return __builtin_amdgcn_rcpf(u); }
+// Reciprocal with one Newton step: the estimate's relative error (below 5e-8
+// measured) squares to a few 1e-15, ample where the values are stored as
+// float32 afterwards.
+__device__ __forceinline__ double frcp1(double u) {
+  const double r = __builtin_amdgcn_rcp(u);
+  return fma(r, fma(-u, r, 1.0), r);
+}
 
 // Face coefficient of the hot operator: the harmonic mean through the
 // reciprocal above.  Symmetric in its arguments bit for bit (the product and

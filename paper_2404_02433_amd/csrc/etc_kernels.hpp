@@ -1469,6 +1469,11 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
   const double dlast = (pok && !right) ? (kr[4] * 2.0 - kL) : 0.0;
   const int64_t plane = g.plane;
   const int nsep = Peff - 1;
+  // pivots' reciprocals: float32 rows take one Newton step, float64 rows two
+  auto rcp = [](double u) {
+    if constexpr (sizeof(S) == 4) return frcp1(u);
+    else return frcp(u);
+  };
 
   auto row_ok = [&](int j) { return EXACT ? (j < MAXM - 1 || !right) : (j < lenp); };
   auto load = [&](int tile, S* v, S& vs) {
@@ -1537,7 +1542,7 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
               gj *= -(aoff * iu);
             }
             if (j == (EXACT ? MAXM - 1 : len - 1)) u += dlast;
-            iu = frcp(u);
+            iu = rcp(u);
             invu[j] = iu;
             dprev = f * iu;
             quad += dprev * f;
@@ -1565,7 +1570,7 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
     // separators line by line (thread = line * P + separator): a line's
     // separators sit in P adjacent lanes of one wave, which exchange rows
     // through shared memory with wave-level ordering only, no block barrier.
-    if constexpr (MAXM <= 16) {
+    if constexpr (MAXM <= 16 || EXACT) {
       const int q = tid % P, ls = tid / P;
       const int bs = (tile % ntx) * TB + ls;  // the separator's mode b'
       const bool sep = bs < g.nb && q < nsep;
@@ -1582,7 +1587,7 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
       for (int h = 1; h < nsep; h <<= 1) {
         wave_sync();  // every lane has read the slots the writes below replace
         // each row publishes its L, U, r scaled by its 1/B
-        const double iB = frcp(Bq);
+        const double iB = rcp(Bq);
         if (sep) {
           sh[0][q][ls] = Lq * iB;
           sh[1][q][ls] = Uq * iB;
@@ -1610,9 +1615,9 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
       // separator value x_q (slot 5 of partition q was read only by this thread)
       if (sep) sh[5][q][ls] = rq / Bq;
     } else {
-      // partitions longer than 16 rows (load axes beyond 512): separator q
-      // is taken by the thread of partition q, rows exchanged through
-      // shared memory with block barriers
+      // guarded partitions longer than 16 rows (load axes beyond 512):
+      // separator q is taken by the thread of partition q, rows exchanged
+      // through shared memory with block barriers
       const int q = p;
       const bool sep = line_ok && q < nsep;
       double Lq = 0.0, Bq = 1.0, Uq = 0.0, rq = 0.0;
@@ -1624,7 +1629,7 @@ __device__ __forceinline__ void k_thomas_body(const BG bg, Geo g, RefMedium rm, 
       }
       for (int h = 1; h < nsep; h <<= 1) {
         __syncthreads();  // every read of the previous contents is done
-        const double iB = frcp(Bq);
+        const double iB = rcp(Bq);
         if (sep) {
           sh[0][q][l] = Lq;
           sh[1][q][l] = Uq;
