@@ -80,6 +80,9 @@ struct LaunchCfg {
   int nStride;
   dim3 gridKeff;
   int nKeff;
+  // extrema: tiles of 256 plane positions x chunks of extChunk planes
+  dim3 gridExt;
+  int extChunk, nExt;
 };
 
 }  // namespace
@@ -351,6 +354,15 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   int64_t gk = (g.plane + kThreads - 1) / kThreads;
   lc.nKeff = (int)std::min<int64_t>(gk, 1024);
   lc.gridKeff = dim3(lc.nKeff, ns);
+  // extrema of one instance: about kMaxGridStride blocks, every one a whole
+  // tile of plane positions marching over a chunk of the load axis
+  {
+    const int64_t tiles = (g.plane + kThreads - 1) / kThreads;
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(g.nL, kMaxGridStride / tiles));
+    lc.extChunk = (int)((g.nL + nch - 1) / nch);
+    lc.gridExt = dim3((unsigned)tiles, (unsigned)((g.nL + lc.extChunk - 1) / lc.extChunk));
+    lc.nExt = (int)(lc.gridExt.x * lc.gridExt.y);
+  }
   return lc;
 }
 
@@ -365,6 +377,7 @@ int max_partials_of(const LaunchCfg& lc) {
   m = std::max<int64_t>(m, lc.nThomasMax);
   m = std::max<int64_t>(m, (int64_t)lc.nStride * 12);
   m = std::max<int64_t>(m, (int64_t)lc.nKeff * 2);
+  m = std::max<int64_t>(m, (int64_t)lc.nExt * 12);
   return (int)m;
 }
 
@@ -497,7 +510,7 @@ template <class S> struct Ops {
   }
 
   // Canonical copies of instance `inst` (conductivity components, source)
-  // and its family extrema into the first 12 * nStride partials.
+  // and its family extrema into the first 12 * nExt partials.
   // inst_src: this instance's own conductivity array (isotropic batches
   // whose instances are not back to back), else nullptr
   static etc_status canon(etc_plan* P, const void* const comp_user[3], const double* source, int inst,
@@ -525,7 +538,7 @@ template <class S> struct Ops {
     if (k.hB) k.hB += off;
     Geo g = P->g;
     g.nseg = 1;
-    k_extrema<S><<<P->lc.nStride, kThreads, 0, P->stream>>>(g, k, P->partials);
+    k_extrema<S><<<P->lc.gridExt, kThreads, 0, P->stream>>>(g, k, P->partials, P->lc.extChunk);
     LAUNCHCHK("extrema");
     return ETC_OK;
   }
@@ -1567,7 +1580,7 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
         if (d != axis) order[c++] = d;
       for (int d = 0; d < 3; ++d) comp[d] = pr->kappa[order[d]];
     }
-    std::vector<double> part((size_t)P->lc.nStride * 12);
+    std::vector<double> part((size_t)P->lc.nExt * 12);
     for (int inst = 0; inst < nseg; ++inst) {
       s = (P->prec == ETC_MIXED) ? Ops<float>::canon(P, comp, pr->source, inst, inst_kappa ? inst_kappa[inst] : nullptr)
                                  : Ops<double>::canon(P, comp, pr->source, inst, inst_kappa ? inst_kappa[inst] : nullptr);
@@ -1582,7 +1595,7 @@ static etc_status setup_impl(const etc_problem* pr, etc_dtype dt, const int64_t 
         mn[f] = INFINITY;
         mx[f] = -INFINITY;
       }
-      for (int blk = 0; blk < P->lc.nStride; ++blk) {
+      for (int blk = 0; blk < P->lc.nExt; ++blk) {
         for (int f = 0; f < 5; ++f) {
           mn[f] = std::fmin(mn[f], part[(size_t)blk * 12 + 2 * f]);
           mx[f] = std::fmax(mx[f], part[(size_t)blk * 12 + 2 * f + 1]);

@@ -144,81 +144,104 @@ __global__ void k_decanon_axis2(const double* __restrict__ src, double* __restri
   }
 }
 
+// Conductivity reads of k_extrema with one storage type for the three
+// families; ISO: one array for all three (one load per voxel and neighbour).
+template <class T, bool ISO> struct KapRead {
+  const T *L, *A, *B;
+  __device__ __forceinline__ double dL(int64_t i) const { return (double)L[i]; }
+  __device__ __forceinline__ double dA(int64_t i) const { return (double)(ISO ? L : A)[i]; }
+  __device__ __forceinline__ double dB(int64_t i) const { return (double)(ISO ? L : B)[i]; }
+};
+
+template <class KA>
+__device__ __forceinline__ void extrema_walk(const Geo& g, const KA& kp, int kchunk, double (&mn)[5],
+                                             double (&mx)[5], double& bad) {
+  {
+    const int nblk = gridDim.x * gridDim.y;
+    const int id = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, nblk);
+    const int tile = id % gridDim.x, chunk = id / gridDim.x;
+    const int64_t pos = (int64_t)tile * blockDim.x + threadIdx.x;
+    const int k0 = chunk * kchunk, k1 = min(g.nL, k0 + kchunk);
+    if (pos < g.plane) {
+      const int a = (int)(pos / g.nb), b = (int)(pos - (int64_t)a * g.nb);
+      double prev = k0 > 0 ? kp.dL((int64_t)(k0 - 1) * g.plane + pos) : 1.0;
+      constexpr int UX = 4;  // planes per trip, all loads issued before any use
+      for (int kb = k0; kb < k1; kb += UX) {
+        double kc[UX], ka[UX], kbb[UX], na_[UX], nb_[UX];
+#pragma unroll
+        for (int u = 0; u < UX; ++u) {
+          if (kb + u < k1) {
+            const int64_t i = (int64_t)(kb + u) * g.plane + pos;
+            kc[u] = kp.dL(i);
+            ka[u] = kp.dA(i);
+            kbb[u] = kp.dB(i);
+            na_[u] = a > 0 ? kp.dA(i - g.nb) : 1.0;
+            nb_[u] = b > 0 ? kp.dB(i - 1) : 1.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UX; ++u) {
+          const int k = kb + u;
+          if (k >= k1) continue;
+          if (!(kc[u] > 0.0) || !isfinite(kc[u]) || !(ka[u] > 0.0) || !isfinite(ka[u]) || !(kbb[u] > 0.0) ||
+              !isfinite(kbb[u]))
+            bad += 1.0;
+          if (k > 0) {
+            const double t = g.fL * hface(kc[u], prev);
+            mn[0] = fmin(mn[0], t);
+            mx[0] = fmax(mx[0], t);
+          }
+          prev = kc[u];
+          if (a > 0) {
+            const double t = g.fa * hface(ka[u], na_[u]);
+            mn[1] = fmin(mn[1], t);
+            mx[1] = fmax(mx[1], t);
+          }
+          if (b > 0) {
+            const double t = g.fb * hface(kbb[u], nb_[u]);
+            mn[2] = fmin(mn[2], t);
+            mx[2] = fmax(mx[2], t);
+          }
+          if (k == 0) {
+            mn[3] = fmin(mn[3], g.fL * kc[u]);
+            mx[3] = fmax(mx[3], g.fL * kc[u]);
+          }
+          if (k == g.nL - 1) {
+            mn[4] = fmin(mn[4], g.fL * kc[u]);
+            mx[4] = fmax(mx[4], g.fL * kc[u]);
+          }
+        }
+      }
+    }
+  }
+}
+
 // Extrema of the five coefficient families (scaled harmonic faces normal to
 // L, a, b; scaled load-axis conductivity of the first and last layers) and a
 // count of invalid conductivities (<= 0, NaN, Inf).  12 partials per block:
 // [minL maxL mina maxa minb maxb minin maxin minout maxout invalid unused].
+// Block (256 threads) = 256 consecutive positions of a plane, marching over
+// a chunk of `kchunk` planes (grid: plane tiles x chunks, tiles of one XCD
+// adjacent): the load-axis neighbour is the thread's previous value and the
+// a and b neighbours lie in lines that this XCD's blocks read at about the
+// same time, so each conductivity comes from HBM about once.
 template <class S>
-__global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __restrict__ partials, int kchunk) {
   double mn[5], mx[5];
   for (int f = 0; f < 5; ++f) {
     mn[f] = __builtin_huge_val();
     mx[f] = -__builtin_huge_val();
   }
   double bad = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const bool small = g.V < ((int64_t)1 << 31);  // 32-bit index splits
-  // UX voxels per thread and trip, all loads issued before any use
-  constexpr int UX = 4;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < g.V; i0 += UX * stride) {
-    int64_t kk[UX], aa[UX], bb[UX];
-    double kc[UX], ka[UX], kb[UX], nl[UX], na_[UX], nb_[UX];
-#pragma unroll
-    for (int u = 0; u < UX; ++u) {
-      const int64_t i = i0 + u * stride;
-      kk[u] = -1;
-      if (i < g.V) {
-        if (small) {
-          const uint32_t iu = (uint32_t)i, pl = (uint32_t)g.plane, nb = (uint32_t)g.nb;
-          const uint32_t k32 = iu / pl, rem = iu - k32 * pl, a32 = rem / nb;
-          kk[u] = k32;
-          aa[u] = a32;
-          bb[u] = rem - a32 * nb;
-        } else {
-          kk[u] = i / g.plane;
-          const int64_t rem = i - kk[u] * g.plane;
-          aa[u] = rem / g.nb;
-          bb[u] = rem - aa[u] * g.nb;
-        }
-        kc[u] = kp.dL(i);
-        ka[u] = kp.dA(i);
-        kb[u] = kp.dB(i);
-        nl[u] = kk[u] > 0 ? kp.dL(i - g.plane) : 1.0;
-        na_[u] = aa[u] > 0 ? kp.dA(i - g.nb) : 1.0;
-        nb_[u] = bb[u] > 0 ? kp.dB(i - 1) : 1.0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < UX; ++u) {
-      if (kk[u] < 0) continue;
-      const int64_t k = kk[u];
-      if (!(kc[u] > 0.0) || !isfinite(kc[u]) || !(ka[u] > 0.0) || !isfinite(ka[u]) || !(kb[u] > 0.0) ||
-          !isfinite(kb[u]))
-        bad += 1.0;
-      if (k > 0) {
-        const double t = g.fL * hface(kc[u], nl[u]);
-        mn[0] = fmin(mn[0], t);
-        mx[0] = fmax(mx[0], t);
-      }
-      if (aa[u] > 0) {
-        const double t = g.fa * hface(ka[u], na_[u]);
-        mn[1] = fmin(mn[1], t);
-        mx[1] = fmax(mx[1], t);
-      }
-      if (bb[u] > 0) {
-        const double t = g.fb * hface(kb[u], nb_[u]);
-        mn[2] = fmin(mn[2], t);
-        mx[2] = fmax(mx[2], t);
-      }
-      if (k == 0) {
-        mn[3] = fmin(mn[3], g.fL * kc[u]);
-        mx[3] = fmax(mx[3], g.fL * kc[u]);
-      }
-      if (k == g.nL - 1) {
-        mn[4] = fmin(mn[4], g.fL * kc[u]);
-        mx[4] = fmax(mx[4], g.fL * kc[u]);
-      }
-    }
+  // the float64 copy of the mixed form when there is one, else the stored arrays
+  if (kp.hL && kp.hA && kp.hB) {
+    if (kp.hA == kp.hL && kp.hB == kp.hL) extrema_walk(g, KapRead<double, true>{kp.hL, kp.hA, kp.hB}, kchunk, mn, mx, bad);
+    else extrema_walk(g, KapRead<double, false>{kp.hL, kp.hA, kp.hB}, kchunk, mn, mx, bad);
+  } else if (!kp.hL && !kp.hA && !kp.hB) {
+    if (kp.A == kp.L && kp.B == kp.L) extrema_walk(g, KapRead<S, true>{kp.L, kp.A, kp.B}, kchunk, mn, mx, bad);
+    else extrema_walk(g, KapRead<S, false>{kp.L, kp.A, kp.B}, kchunk, mn, mx, bad);
+  } else {
+    extrema_walk(g, kp, kchunk, mn, mx, bad);
   }
   __shared__ double red[12][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -244,7 +267,7 @@ __global__ __launch_bounds__(256) void k_extrema(Geo g, Kap<S> kp, double* __res
       else if (q & 1) v = fmax(v, red[q][w]);
       else v = fmin(v, red[q][w]);
     }
-    partials[(int64_t)blockIdx.x * 12 + q] = v;
+    partials[(int64_t)(blockIdx.x + gridDim.x * blockIdx.y) * 12 + q] = v;
   }
 }
 
