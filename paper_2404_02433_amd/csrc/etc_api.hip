@@ -40,7 +40,11 @@ etc_status fail(etc_status s, const std::string& msg) {
 constexpr int kThreads = 256;
 // isotropic stencil tile (b x a): 128 x 16 for float32 storage, 64 x 16 for
 // float64 (whose larger register footprint keeps the smaller block)
-constexpr int stencil_tbw(size_t elt) { return elt == 4 ? 128 : 64; }
+// Isotropic stencil tile width (b): float32 lines longer than 256 take 128
+// (fewer halo lines: 0.35 against 0.36 ms at 512^3), shorter ones 64 (fewer
+// idle lanes on ragged tiles: 48^3 to 256^3 run 3-22 % faster); float64
+// keeps 64 (register footprint).
+constexpr int stencil_tbw(size_t elt, int nb) { return (elt == 4 && nb > 256) ? 128 : 64; }
 constexpr int kStencilTAH = 16;
 constexpr int kMaxGridStride = 2048;   // grid of the grid-stride reduction kernels
 constexpr int kThomasP = 32;           // most partitions per line in the tridiagonal kernel
@@ -298,7 +302,7 @@ LaunchCfg make_launch(const Geo& g, const DctPlan& dpa, const DctPlan& dpb, size
   // with chunks of at least 16 planes, and go down to 8 planes while there
   // are fewer than 512 (single RVEs up to 128^3: 22 instead of 32 us at
   // 128^3, while 8-plane chunks at 256^3 are no faster)
-  lc.stencilTBW = ortho ? 64 : stencil_tbw(elt);
+  lc.stencilTBW = ortho ? 64 : stencil_tbw(elt, g.nb);
   const int gx = (g.nb + lc.stencilTBW - 1) / lc.stencilTBW, gy = (g.na + kStencilTAH - 1) / kStencilTAH;
   const int64_t cols = (int64_t)gx * gy * ns;
   int kchunk = g.nL;
@@ -1026,10 +1030,12 @@ template <class S> struct Ops {
     const LaunchCfg& lc = P->lc;
     if (P->ortho)
       k_apply_A<S, S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
+    else if (sizeof(S) == 4 && lc.stencilTBW == 128)
+      k_apply_A_iso<S, false, S, 128, kStencilTAH><<<lc.gridA, dim3(128, kStencilTAH / 4), 0, P->stream>>>(
+          P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y, partials, st, gate, lc.kchunk);
     else
-      k_apply_A_iso<S, false, S, stencil_tbw(sizeof(S)), kStencilTAH>
-          <<<lc.gridA, dim3(stencil_tbw(sizeof(S)), kStencilTAH / 4), 0, P->stream>>>(P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y,
-                                                                 partials, st, gate, lc.kchunk);
+      k_apply_A_iso<S, false, S, 64, kStencilTAH><<<lc.gridA, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
+          P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y, partials, st, gate, lc.kchunk);
     LAUNCHCHK("apply_A");
     return ETC_OK;
   }
@@ -1128,8 +1134,11 @@ template <class S> struct Ops {
       m.a[gi] = StencilArgs<S, S, S>{P->g, (const S*)P->w, kap(P), (const S*)P->kap_s[0], rhs(P), (S*)P->q,
                                      P->partials, P->st, P->lc.kchunk};
     }
-    constexpr int TBW = stencil_tbw(sizeof(S));
-    k_apply_A_iso_multi<S, false, S, TBW, kStencilTAH><<<tot, dim3(TBW, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
+    // one tile width for all groups (etc_setup_ensemble makes them agree)
+    if (sizeof(S) == 4 && E->groups[0]->lc.stencilTBW == 128)
+      k_apply_A_iso_multi<S, false, S, 128, kStencilTAH><<<tot, dim3(128, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
+    else
+      k_apply_A_iso_multi<S, false, S, 64, kStencilTAH><<<tot, dim3(64, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
     LAUNCHCHK("apply_A_multi");
     return ETC_OK;
   }
@@ -1957,6 +1966,19 @@ etc_status etc_setup_ensemble(const void* const* kappa, const int64_t* dims, int
       return fail(s, msg);
     }
     E->groups.push_back(G);
+  }
+  // the isotropic stencil runs as one launch for all groups: one tile width
+  // (128 if any group's lines are long enough for it; wider tiles need fewer
+  // partial sums, so every group's buffers still suffice)
+  {
+    int tbw = 64;
+    for (etc_plan* G : E->groups)
+      if (!G->ortho) tbw = std::max(tbw, G->lc.stencilTBW);
+    for (etc_plan* G : E->groups)
+      if (!G->ortho && G->lc.stencilTBW != tbw) {
+        G->lc.stencilTBW = tbw;
+        set_stencil_chunk(G->lc, G->g, G->lc.kchunk);
+      }
   }
   E->inst_group = L.inst_group;
   E->inst_local = L.inst_local;
