@@ -49,16 +49,21 @@ def test_operator_matches_oracle_fp64(shape, axis):
     plan.close()
 
 
-def test_operator_matches_oracle_mixed():
-    shape = (33, 21, 66)
+# float32 lines of 66 take 64-wide stencil tiles (one ragged), lines of 300
+# 128-wide ones (the last 44 wide)
+@pytest.mark.parametrize("shape", [(33, 21, 66), (9, 21, 300)])
+def test_operator_matches_oracle_mixed(shape):
     kap = rvegen.random_two_phase(shape, seed=4, kappa=(1.0, 100.0))
     plan = etc.etc_setup(dev(kap), 0, precision="mixed")
     pb = O.make_problem(kap, 0)
     x = np.random.default_rng(2).standard_normal(pb.shape).astype(np.float32)
-    y = etc.etc_apply_A(plan, dev(x, torch.float32))
+    y, d = etc.etc_apply_A(plan, dev(x, torch.float32), want_dot=True)
     ref = O.apply_A(pb, x.astype(np.float64))
     err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
     assert err < 2e-6, err
+    # w . q from the float32 products summed in float64 per tile
+    dref = float(np.vdot(x.astype(np.float64), ref))
+    assert abs(d - dref) < 1e-5 * abs(dref), (d, dref)
     plan.close()
 
 
