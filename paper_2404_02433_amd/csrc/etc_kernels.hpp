@@ -1270,7 +1270,13 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
   // forward inputs: 16-byte loads of VW adjacent columns (whole tiles)
   constexpr int VW = 16 / (int)sizeof(S), CQ = TBV / VW, RPR = NTHR / CQ, UV = N / RPR;
   static_assert(TBV % VW == 0 && NTHR % CQ == 0 && N % RPR == 0, "forward load shape");
-  constexpr int NV = DIR < 0 ? 1 : 4 * UI;
+  // backward inputs of float32 columns of 256 or more: 16-byte loads as well,
+  // VW adjacent columns of one item's four rows (items4 pairs of column group
+  // and item); 271 against 277 us at 512^3.  Shorter or float64 columns keep
+  // one column per lane (the wider loads cost them occupancy or registers).
+  constexpr bool BV = DIR > 0 && sizeof(S) == 4 && NC >= 256;
+  constexpr int IQ = TBV / VW, items4 = IQ * (M / 2 + 1), UB = (items4 + NTHR - 1) / NTHR;
+  constexpr int NV = (DIR < 0 || BV) ? 1 : 4 * UI;
   if (gated_out(st, gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -1302,6 +1308,7 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
     pl = data + (int64_t)plane * g.plane + b0;
   };
   S x[NV];
+  V16<S> xb[BV ? UB : 1][4];
   V16<S> xv[DIR < 0 ? UV : 1];
   auto load = [&](const S* pl, int last, uint32_t nb) {
     const uint32_t c = (uint32_t)min(tid % TBV, last);
@@ -1309,6 +1316,21 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
       const uint32_t c4 = VW * (uint32_t)(tid % CQ), r0 = (uint32_t)(tid / CQ);
 #pragma unroll
       for (int u = 0; u < UV; ++u) xv[u] = ld16(pl + (r0 + (uint32_t)(u * RPR)) * nb + c4);
+    } else if constexpr (BV) {
+      (void)c;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int e = tid + u * NTHR;
+        if (e < items4) {
+          int i0, i1, i2, i3;
+          const uint32_t c4 = VW * (uint32_t)(e % IQ);
+          pre_inv_idx(e / IQ, N, M, i0, i1, i2, i3);
+          xb[u][0] = ld16(pl + (uint32_t)i0 * nb + c4);
+          xb[u][1] = ld16(pl + (uint32_t)i1 * nb + c4);
+          xb[u][2] = ld16(pl + (uint32_t)i2 * nb + c4);
+          xb[u][3] = ld16(pl + (uint32_t)i3 * nb + c4);
+        }
+      }
     } else {
 #pragma unroll
       for (int u = 0; u < UI; ++u) {
@@ -1334,6 +1356,18 @@ __global__ __launch_bounds__((DctShape<T, NC>::col_threads), (DctShape<T, NC>::c
         const int pos = vpos(dct_perm(r0 + u * RPR, N));
 #pragma unroll
         for (int j = 0; j < VW; ++j) reinterpret_cast<T*>(buf + (c4 + j) * LS)[pos] = (T)xv[u].v[j];
+      }
+    } else if constexpr (BV) {
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int e = tid + u * NTHR;
+        if (e < items4) {
+          const int k = e / IQ, c4 = VW * (e % IQ);
+#pragma unroll
+          for (int j = 0; j < VW; ++j)
+            dct_pre_inv_vals(buf + (c4 + j) * LS, k, M, twd, (T)xb[u][0].v[j], (T)xb[u][1].v[j], (T)xb[u][2].v[j],
+                             (T)xb[u][3].v[j]);
+        }
       }
     } else {
       const int c = tid % TBV;
