@@ -489,8 +489,10 @@ __device__ __forceinline__ void k_apply_A_iso_body(const BG bg, Geo g, const typ
     if (RES && rh.src) rh.src += off;
   }
   static_assert(TAH % ARPT == 0 && TAH >= 16 && TBW >= TAH && TBW % 64 == 0, "tile shape");
-  __shared__ C tw_[TAH + 2][TBW + 2];
-  __shared__ C tk_[TAH + 2][TBW + 2];
+  // two LDS planes, used alternately: a plane is written while the previous
+  // one may still be read, so one barrier per plane suffices
+  __shared__ C tw2_[2][TAH + 2][TBW + 2];
+  __shared__ C tk2_[2][TAH + 2][TBW + 2];
   __shared__ double red[16];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int b0 = bx * TBW, a0 = by * TAH;
@@ -560,7 +562,10 @@ __device__ __forceinline__ void k_apply_A_iso_body(const BG bg, Geo g, const typ
       knn[j] = ld(ks, k + 2, col[j], rok[j] && more, C(1));
     }
     const C hwn = ld(w, k + 1, hcol, hok && more, C(0)), hkn = ld(ks, k + 1, hcol, hok && more, C(1));
-    __syncthreads();  // previous plane's LDS reads are done
+    // this plane's buffer was last read two planes ago, before the barrier
+    // that followed the previous plane's writes
+    C(&tw_)[TAH + 2][TBW + 2] = tw2_[(k - k0) & 1];
+    C(&tk_)[TAH + 2][TBW + 2] = tk2_[(k - k0) & 1];
 #pragma unroll
     for (int j = 0; j < ARPT; ++j) {
       tw_[rbase + j][1 + tx] = wc[j];
