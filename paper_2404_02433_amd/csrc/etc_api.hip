@@ -1030,12 +1030,19 @@ template <class S> struct Ops {
     const LaunchCfg& lc = P->lc;
     if (P->ortho)
       k_apply_A<S, S, true><<<lc.gridA, dim3(64, 4), 0, P->stream>>>(P->g, x, kap(P), y, partials, st, gate, lc.kchunk);
-    else if (sizeof(S) == 4 && lc.stencilTBW == 128)
-      k_apply_A_iso<S, false, S, 128, kStencilTAH><<<lc.gridA, dim3(128, kStencilTAH / 4), 0, P->stream>>>(
-          P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y, partials, st, gate, lc.kchunk);
-    else
-      k_apply_A_iso<S, false, S, 64, kStencilTAH><<<lc.gridA, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
-          P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y, partials, st, gate, lc.kchunk);
+    else {
+      auto launch = [&](auto tbw) {
+        constexpr int TBW = decltype(tbw)::value;
+        k_apply_A_iso<S, false, S, TBW, kStencilTAH><<<lc.gridA, dim3(TBW, kStencilTAH / 4), 0, P->stream>>>(
+            P->g, x, kap(P), (const S*)P->kap_s[0], rhs(P), y, partials, st, gate, lc.kchunk);
+      };
+      if constexpr (sizeof(S) == 4) {
+        if (lc.stencilTBW == 128) launch(std::integral_constant<int, 128>{});
+        else launch(std::integral_constant<int, 64>{});
+      } else {
+        launch(std::integral_constant<int, 64>{});
+      }
+    }
     LAUNCHCHK("apply_A");
     return ETC_OK;
   }
@@ -1048,14 +1055,25 @@ template <class S> struct Ops {
     if (P->ortho)
       k_residual<S, true><<<lc.gridR, dim3(64, 4), 0, P->stream>>>(P->g, P->p, kap(P), rhs(P), r, P->partials, st, gate,
                                                                    lc.kchunkR);
-    else if (P->kap_hi[0])  // float64 copy of a float64 input
-      k_apply_A_iso<S, true, double, 64, kStencilTAH>
-          <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
-          P->g, P->p, kap(P), P->kap_hi[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
-    else
-      k_apply_A_iso<S, true, S, 64, kStencilTAH>
-          <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
-          P->g, P->p, kap(P), (const S*)P->kap_s[0], rhs(P), r, P->partials, st, gate, lc.kchunk);
+    else {
+      // kappa at its input precision (the float64 copy of a float64 input);
+      // without a source and face data b needs no reads of its own
+      const bool plain = !P->src && !P->pin_face && !P->pout_face;
+      auto launch = [&](auto kt, auto pl) {
+        using KT = decltype(kt);
+        k_apply_A_iso<S, true, KT, 64, kStencilTAH, decltype(pl)::value>
+            <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
+                P->g, P->p, kap(P), P->kap_hi[0] ? (const KT*)(const void*)P->kap_hi[0] : (const KT*)P->kap_s[0],
+                rhs(P), r, P->partials, st, gate, lc.kchunk);
+      };
+      if (P->kap_hi[0]) {
+        if (plain) launch(double{}, std::true_type{});
+        else launch(double{}, std::false_type{});
+      } else {
+        if (plain) launch(S{}, std::true_type{});
+        else launch(S{}, std::false_type{});
+      }
+    }
     LAUNCHCHK("residual");
     return ETC_OK;
   }
@@ -1135,10 +1153,16 @@ template <class S> struct Ops {
                                      P->partials, P->st, P->lc.kchunk};
     }
     // one tile width for all groups (etc_setup_ensemble makes them agree)
-    if (sizeof(S) == 4 && E->groups[0]->lc.stencilTBW == 128)
-      k_apply_A_iso_multi<S, false, S, 128, kStencilTAH><<<tot, dim3(128, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
-    else
-      k_apply_A_iso_multi<S, false, S, 64, kStencilTAH><<<tot, dim3(64, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
+    auto launch = [&](auto tbw) {
+      constexpr int TBW = decltype(tbw)::value;
+      k_apply_A_iso_multi<S, false, S, TBW, kStencilTAH><<<tot, dim3(TBW, kStencilTAH / 4), 0, E->stream>>>(gm, m, 1);
+    };
+    if constexpr (sizeof(S) == 4) {
+      if (E->groups[0]->lc.stencilTBW == 128) launch(std::integral_constant<int, 128>{});
+      else launch(std::integral_constant<int, 64>{});
+    } else {
+      launch(std::integral_constant<int, 64>{});
+    }
     LAUNCHCHK("apply_A_multi");
     return ETC_OK;
   }
@@ -1155,7 +1179,12 @@ template <class S> struct Ops {
       const KT* ks = std::is_same<KT, double>::value ? (const KT*)(const void*)P->kap_hi[0] : (const KT*)P->kap_s[0];
       m.a[gi] = StencilArgs<S, double, KT>{P->g, P->p, kap(P), ks, rhs(P), (S*)P->r, P->partials, P->st, P->lc.kchunk};
     }
-    k_apply_A_iso_multi<S, true, KT, 64, kStencilTAH><<<tot, dim3(64, kStencilTAH / 4), 0, E->stream>>>(gm, m, 2);
+    bool plain = true;  // no group has a source or face data
+    for (etc_plan* P : E->groups) plain = plain && !P->src && !P->pin_face && !P->pout_face;
+    if (plain)
+      k_apply_A_iso_multi<S, true, KT, 64, kStencilTAH, true><<<tot, dim3(64, kStencilTAH / 4), 0, E->stream>>>(gm, m, 2);
+    else
+      k_apply_A_iso_multi<S, true, KT, 64, kStencilTAH><<<tot, dim3(64, kStencilTAH / 4), 0, E->stream>>>(gm, m, 2);
     LAUNCHCHK("residual_multi");
     return ETC_OK;
   }

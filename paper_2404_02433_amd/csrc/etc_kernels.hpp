@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const S* __restrict__ w,
 // RES = true: the float64 true residual r = b - A p of the mixed form (p
 // float64, kappa read as KT, arithmetic in C = double, r stored as S, partial
 // ||r||^2); RES = false: q = A w with the partial w . q, all in S.
-template <class S, bool RES, class KT, int TBW, int TAH, class BG>
+template <class S, bool RES, class KT, int TBW, int TAH, class BG, bool PLAIN = false>
 __device__ __forceinline__ void k_apply_A_iso_body(const BG bg, Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
                                                      Kap<S> kp, const KT* __restrict__ ks, Rhs rh,
                                                      S* __restrict__ q, double* __restrict__ partials,
@@ -613,7 +613,18 @@ __device__ __forceinline__ void k_apply_A_iso_body(const BG bg, Geo g, const typ
       if (rok[j]) {
         const int64_t gi = (int64_t)k * plane + col[j];
         if constexpr (RES) {
-          const S rs = (S)(rhs_at(g, kp, rh, gi, k, col[j]) - qv);
+          // PLAIN: no source and constant Dirichlet data, so b is the
+          // boundary term of the first and last layers, whose conductivity
+          // is this voxel's (the same value rhs_at reads)
+          double bv;
+          if constexpr (PLAIN) {
+            bv = 0.0;
+            if (k == 0) bv += 2.0 * g.fL * (double)kc[j] * g.p_in;
+            if (k == g.nL - 1) bv += 2.0 * g.fL * (double)kc[j] * g.p_out;
+          } else {
+            bv = rhs_at(g, kp, rh, gi, k, col[j]);
+          }
+          const S rs = (S)(bv - qv);
           q[gi] = rs;
           acc += (double)rs * (double)rs;
         } else {
@@ -641,12 +652,12 @@ __device__ __forceinline__ void k_apply_A_iso_body(const BG bg, Geo g, const typ
   }
 }
 
-template <class S, bool RES, class KT, int TBW, int TAH>
+template <class S, bool RES, class KT, int TBW, int TAH, bool PLAIN = false>
 __global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso(Geo g, const typename std::conditional<RES, double, S>::type* __restrict__ w,
                                                      Kap<S> kp, const KT* __restrict__ ks, Rhs rh,
                                                      S* __restrict__ q, double* __restrict__ partials,
                                                      const DevState* __restrict__ st, int gate, int kchunk) {
-  k_apply_A_iso_body<S, RES, KT, TBW, TAH, HwGrid>(HwGrid{}, g, w, kp, ks, rh, q, partials, st, gate, kchunk);
+  k_apply_A_iso_body<S, RES, KT, TBW, TAH, HwGrid, PLAIN>(HwGrid{}, g, w, kp, ks, rh, q, partials, st, gate, kchunk);
 }
 
 // r = b - A p in double arithmetic (p double, kappa at its input precision),
@@ -2280,13 +2291,13 @@ template <class S, class W, class KT> struct StencilArgs {
 };
 template <class S, class W, class KT> struct StencilMulti { StencilArgs<S, W, KT> a[kMaxGroups]; };
 
-template <class S, bool RES, class KT, int TBW, int TAH>
+template <class S, bool RES, class KT, int TBW, int TAH, bool PLAIN = false>
 __global__ __launch_bounds__(TBW*(TAH / 4)) void k_apply_A_iso_multi(
     GroupMap gm, StencilMulti<S, typename std::conditional<RES, double, S>::type, KT> m, int gate) {
   SubGrid sg;
   const auto& x = m.a[gm.find(sg)];
-  k_apply_A_iso_body<S, RES, KT, TBW, TAH, SubGrid>(sg, x.g, x.w, x.kp, x.ks, x.rh, x.q, x.partials, x.st, gate,
-                                                   x.kchunk);
+  k_apply_A_iso_body<S, RES, KT, TBW, TAH, SubGrid, PLAIN>(sg, x.g, x.w, x.kp, x.ks, x.rh, x.q, x.partials, x.st,
+                                                          gate, x.kchunk);
 }
 
 template <class S, class T> struct RowsArgs {
