@@ -38,12 +38,10 @@ etc_status fail(etc_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kThreads = 256;
-// isotropic stencil tile (b x a): 128 x 16 for float32 storage, 64 x 16 for
-// float64 (whose larger register footprint keeps the smaller block)
-// Isotropic stencil tile width (b): float32 lines longer than 256 take 128
-// (fewer halo lines: 0.35 against 0.36 ms at 512^3), shorter ones 64 (fewer
-// idle lanes on ragged tiles: 48^3 to 256^3 run 3-22 % faster); float64
-// keeps 64 (register footprint).
+// Isotropic stencil tile width (b; tiles of 16 a rows): float32 lines
+// longer than 256 take 128 (fewer halo lines: 0.35 against 0.36 ms at
+// 512^3), shorter ones 64 (fewer idle lanes on ragged tiles: 48^3 to 256^3
+// run 3-22 % faster); float64 keeps 64 (register footprint).
 constexpr int stencil_tbw(size_t elt, int nb) { return (elt == 4 && nb > 256) ? 128 : 64; }
 constexpr int kStencilTAH = 16;
 constexpr int kMaxGridStride = 2048;   // grid of the grid-stride reduction kernels
@@ -1059,19 +1057,19 @@ template <class S> struct Ops {
       // kappa at its input precision (the float64 copy of a float64 input);
       // without a source and face data b needs no reads of its own
       const bool plain = !P->src && !P->pin_face && !P->pout_face;
-      auto launch = [&](auto kt, auto pl) {
-        using KT = decltype(kt);
+      auto launch = [&](auto pl, const auto* ks) {
+        using KT = typename std::remove_cv<typename std::remove_pointer<decltype(ks)>::type>::type;
         k_apply_A_iso<S, true, KT, 64, kStencilTAH, decltype(pl)::value>
-            <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(
-                P->g, P->p, kap(P), P->kap_hi[0] ? (const KT*)(const void*)P->kap_hi[0] : (const KT*)P->kap_s[0],
-                rhs(P), r, P->partials, st, gate, lc.kchunk);
+            <<<lc.gridRes, dim3(64, kStencilTAH / 4), 0, P->stream>>>(P->g, P->p, kap(P), ks, rhs(P), r, P->partials,
+                                                                      st, gate, lc.kchunk);
       };
-      if (P->kap_hi[0]) {
-        if (plain) launch(double{}, std::true_type{});
-        else launch(double{}, std::false_type{});
+      if (const double* hi = P->kap_hi[0]) {
+        if (plain) launch(std::true_type{}, hi);
+        else launch(std::false_type{}, hi);
       } else {
-        if (plain) launch(S{}, std::true_type{});
-        else launch(S{}, std::false_type{});
+        const S* ks = (const S*)P->kap_s[0];
+        if (plain) launch(std::true_type{}, ks);
+        else launch(std::false_type{}, ks);
       }
     }
     LAUNCHCHK("residual");
