@@ -206,6 +206,9 @@ DctPlan make_dct_plan(int N) {
   dp.M = N / 2;
   dp.fft = 0;
   if (N >= 2 && N % 2 == 0 && factor_radices(N / 2, dp)) dp.fft = 1;
+  // lines too long for one pass of a stage even one at a time take the
+  // direct route
+  if (dp.fft && fft_lines_cap(dp.M, 256) < 1) dp.fft = 0;
   if (dp.fft) {
     dp.lstride = fft_lstride(dp.M);  // complex slots per line
   } else {

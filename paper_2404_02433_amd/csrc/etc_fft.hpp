@@ -257,14 +257,30 @@ __host__ __device__ constexpr int fft_lstride(int M) {
   return (ls % 2 == 0) ? ls + 1 : ls;
 }
 
+// Most lines that one pass of every stage of an M-point FFT covers with
+// nthr threads: a radix-R stage of the run-time route holds 16 / R (at
+// least 1) butterflies per thread, so lines * (M / R) <= (16 / R) * nthr
+// for each radix of the plan (radices 3 and 5 bind below lines * M = 16 nthr).
+// 0 when not even one line fits.
+__host__ __device__ constexpr int fft_lines_cap(int M, int nthr) {
+  const RadixPlan p = radix_plan(M);
+  int c = 16 * nthr / M;
+  for (int i = 0; i < p.n; ++i) {
+    const int R = p.r[i];
+    const int ci = (R >= 16 ? 1 : 16 / R) * nthr / (M / R);
+    if (ci < c) c = ci;
+  }
+  return c;
+}
+
 // Lines per block of the row transforms (256 threads): an LDS budget of
-// 48 KiB and at most 16 complex values per thread and stage.
+// 48 KiB and one pass of every FFT stage.
 __host__ __device__ constexpr int rows_lines(int M, int ls, int elt, bool fft) {
   const int line_bytes = ls * 2 * elt;
   int r = (48 * 1024) / line_bytes;
   if (r < 1) r = 1;
   if (fft) {
-    int c = 16 * 256 / M;
+    int c = fft_lines_cap(M, 256);
     if (c < 1) c = 1;
     if (c < r) r = c;
   }
@@ -272,15 +288,15 @@ __host__ __device__ constexpr int rows_lines(int M, int ls, int elt, bool fft) {
 }
 
 // Columns per block of the column transforms (256 threads in float64, 512 in
-// float32): an LDS budget of 80 KiB, at most 16 complex values per thread and
-// stage, 16 or 32 columns when they fit (whole 128-byte rows).
+// float32): an LDS budget of 80 KiB, one pass of every FFT stage, 16 or 32
+// columns when they fit (whole 128-byte rows).
 __host__ __device__ constexpr int cols_threads(int elt) { return elt == 4 ? 512 : 256; }
 __host__ __device__ constexpr int cols_tile(int M, int ls, int elt, bool fft) {
   const int line_bytes = ls * 2 * elt;
   int tb = (80 * 1024) / line_bytes;
   if (tb < 1) tb = 1;
   if (fft) {
-    int c = 16 * cols_threads(elt) / M;
+    int c = fft_lines_cap(M, cols_threads(elt));
     if (c < 1) c = 1;
     if (c < tb) tb = c;
   }

@@ -124,3 +124,28 @@ def test_one_launch_ensemble_spans_tridiagonal_block_sizes(precision):
         # these thin RVEs is within 2e-5 of the truth
         tol = 1e-9 if precision == "fp64" else 1e-4
         assert abs(one["keff"][i] - ref["keff"]) <= tol * ref["keff"], (i, one["keff"][i], ref["keff"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_launch_ensemble_with_one_stencil_width_for_all_groups(precision):
+    """float32 lines longer than 256 take 128-wide stencil tiles, shorter
+    ones 64: an ensemble mixing both runs every group at 128 in its single
+    stencil launch (float64 keeps 64 everywhere).  K_eff against the oracle
+    and against the RVEs' own batch plans, which keep their own width."""
+    shapes = [(20, 6, 300), (16, 8, 40), (12, 5, 270), (16, 8, 40)]
+    rng = np.random.default_rng(91)
+    kaps = [np.exp(0.8 * rng.standard_normal(s)) for s in shapes]
+    dtype = torch.float32 if precision == "mixed" else torch.float64
+    tk = [torch.as_tensor(k, dtype=dtype, device="cuda:0") for k in kaps]
+    rtol = 1e-12 if precision == "fp64" else 1e-6
+    print(f"ensemble stencil widths {precision} {shapes}", flush=True)
+    one = etc.solve_ensemble(tk, 0, precision=precision, rtol=rtol)
+    per = etc.solve_ensemble(tk, 0, precision=precision, rtol=rtol, mode="plans", concurrent=False)
+    for i, k in enumerate(kaps):
+        kin = k.astype(np.float32).astype(np.float64) if precision == "mixed" else k
+        ref = O.solve(kin, 0, rtol=1e-12)
+        assert one["status"][i] == "ok"
+        assert abs(one["iters"][i] - per["iters"][i]) <= 1, i
+        assert abs(one["keff"][i] - per["keff"][i]) <= (1e-11 if precision == "fp64" else 1e-6) * per["keff"][i], i
+        tol = 1e-9 if precision == "fp64" else 1e-4
+        assert abs(one["keff"][i] - ref["keff"]) <= tol * ref["keff"], (i, one["keff"][i], ref["keff"])

@@ -84,6 +84,8 @@ PRECOND_SHAPES = [
     (3, 256, 160),   # compile-time column length 256, row length 160
     (2, 48, 512),    # compile-time column length 48, row length 512
     (300, 3, 5),     # ragged partitions (no exact variant), 10 rows each
+    (4, 500, 6),     # 500 -> M=250 (2x5x5x5): 16 columns would need 4 radix-5 butterflies per thread
+    (3, 486, 4),     # 486 -> M=243 (3^5): 16 columns would need 6 radix-3 butterflies per thread
 ]
 
 
@@ -161,8 +163,15 @@ def test_tridiagonal_shape_that_does_not_hold_the_axis_is_rejected():
         plan.close()
 
 
+# Run-time FFT lengths whose radix-3 or radix-5 stages bound the lines per
+# block below 16 complex values per thread: rows of 300 (M=150), 270 (135),
+# 200 (100) and 384 (192), columns of 500 (250) and 486 (243).
+FFT_RADIX_BOUND = [(20, 6, 300), (12, 5, 270), (20, 6, 200), (20, 6, 384), (4, 500, 6), (3, 486, 4)]
+
+
 @pytest.mark.parametrize("shape", [(96, 8, 12), (256, 4, 16), (3, 256, 160), (2, 48, 512), (300, 3, 5), (64, 6, 40),
-                                   (33, 16, 16), (4, 128, 64), (5, 512, 32), (3, 512, 40), (2, 64, 160)])
+                                   (33, 16, 16), (4, 128, 64), (5, 512, 32), (3, 512, 40), (2, 64, 160)]
+                         + FFT_RADIX_BOUND)
 def test_preconditioner_mixed_shapes(shape):
     """float32 storage: compile-time (one-instance plans: persistent column)
     kernels, exact and ragged tridiagonal partitions."""
