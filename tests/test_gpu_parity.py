@@ -186,6 +186,45 @@ def test_preconditioner_mixed_shapes(shape):
     plan.close()
 
 
+def _five_smooth(m):
+    for r in (2, 3, 5):
+        while m % r == 0:
+            m //= r
+    return m == 1
+
+
+# Every FFT-route length up to 640 (N even, N/2 with no prime factor above 5)
+# and a few dense-route ones, as rows (64 lines: row blocks at their largest)
+# and as columns (32 columns: column tiles at their widest).
+FFT_SWEEP = [n for n in range(4, 641, 2) if _five_smooth(n // 2)] + [7, 34, 101, 257, 514]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("where", ["rows", "cols"])
+def test_preconditioner_every_fft_length(precision, where):
+    mixed = precision == "mixed"
+    tdt = torch.float32 if mixed else torch.float64
+    bad = []
+    for n in FFT_SWEEP:
+        shape = (8, 8, n) if where == "rows" else (2, n, 32)
+        kap = lognormal(shape, seed=n, sigma=0.5)
+        if mixed:
+            kap = kap.astype(np.float32).astype(np.float64)
+        plan = etc.etc_setup(dev(kap, tdt), 0, precision=precision)
+        r = np.random.default_rng(n).standard_normal(shape)
+        if mixed:
+            r = r.astype(np.float32)
+        z = etc.etc_apply_Minv(plan, dev(r, tdt))
+        plan.close()
+        pb = O.make_problem(kap, 0)
+        ref = O.apply_Aref_inv(r.astype(np.float64), O.kref_mid(pb))
+        err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+        if not err < (1e-5 if mixed else 1e-11):
+            bad.append((n, float(err)))
+    print(f"{where} {precision}: {len(FFT_SWEEP)} lengths, failing {bad}", flush=True)
+    assert not bad, bad
+
+
 def test_preconditioner_mixed_close_to_oracle():
     shape = (32, 64, 96)
     kap = lognormal(shape, seed=8)
